@@ -1,0 +1,162 @@
+/*
+ * sbfem.h -- C ABI of the MI355X explicit octree-SBFEM time stepper.
+ *
+ * The library advances  M u'' + C u' + K u = P(t) b  with the central
+ * difference method on a lumped (diagonal) mass (eq. DnMdiag, Sec. 3.3),
+ * computing the internal force element by element (eq. Rinte) as
+ * R_int = sum_e s_e R_e^T K_p R_e u_e, where K_p is the stiffness of the
+ * unit master cell of pattern p (eq. Rintep), R_e the signed permutation that
+ * maps the cell onto its master (Sec. 3.2.2), and s_e = E_e h_e (eq. KM_scale).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns sbfem_status; 0 is success.  On failure the message
+ *    is available from sbfem_last_error() (per calling thread).
+ *  - Pointers named "host" point to host memory; the library copies what it
+ *    needs before returning and never keeps a caller pointer.  Device memory
+ *    is owned by the library and released by the matching destroy call.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *    Work is enqueued on it; read_state blocks until its copy is complete.
+ *  - Calls on one mesh handle are not thread-safe; different handles are
+ *    independent.  A pattern library must outlive the meshes created from it.
+ *  - dof numbering is node-major: dof = 3*node + axis.
+ */
+#ifndef SBFEM_H
+#define SBFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SBFEM_OK = 0,
+  SBFEM_EINVAL = -1,     /* malformed argument or mesh */
+  SBFEM_ENOMEM = -2,     /* device allocation failed or over the memory budget */
+  SBFEM_EDEVICE = -3,    /* a HIP runtime call failed */
+  SBFEM_EUNSTABLE = -4,  /* non-finite displacement detected (time step too large) */
+  SBFEM_EBUSY = -5
+} sbfem_status;
+
+/* Precision of the element product K_p u_e.  FP32/FP16/BF16 accumulate in FP32. */
+typedef enum { SBFEM_PROD_FP64 = 0, SBFEM_PROD_FP32 = 1, SBFEM_PROD_FP16 = 2, SBFEM_PROD_BF16 = 3 } sbfem_prod;
+/* Storage of the displacement history u_n, u_{n-1}. */
+typedef enum { SBFEM_STATE_FP64 = 0, SBFEM_STATE_FP32 = 1, SBFEM_STATE_KAHAN32 = 2 } sbfem_state;
+/* Assembly of R_int: floating-point atomics, or colour by colour (bitwise reproducible). */
+typedef enum { SBFEM_ASM_ATOMIC = 0, SBFEM_ASM_COLOUR = 1 } sbfem_asm;
+/* Load-time function P(t) (Sec. 5, eqs. Ricker, Triangle, Lamb). */
+typedef enum { SBFEM_LOAD_RICKER = 0, SBFEM_LOAD_TRIANGLE = 1, SBFEM_LOAD_SINE_BURST = 2 } sbfem_load_kind;
+
+typedef struct sbfem_patterns sbfem_patterns;  /* opaque: uploaded master-cell library */
+typedef struct sbfem_mesh sbfem_mesh;          /* opaque: one simulation's resident state */
+
+/*
+ * Orientation code of a cell (0..47), the signed permutation Q with
+ * u_master[k][a] = s_a * u_cell[conn[k]][pi(a)]  (Sec. 3.2.2, transformation
+ * of u and back-transformation of the force with Q^-1 = Q^T):
+ *   code = 8*perm + signs, perm indexes pi in the order
+ *   (0,1,2) (0,2,1) (1,0,2) (1,2,0) (2,0,1) (2,1,0), and bit a of signs set
+ *   means s_a = -1.
+ */
+
+typedef struct {
+  int64_t n_nodes;              /* number of nodes N (3N dofs) */
+  int64_t n_cells;              /* number of cells */
+  double h0;                    /* edge of a level-0 cell; h_e = h0 * 2^-level[e] */
+  const int32_t* conn;          /* host: node ids per cell in master order of its pattern,
+                                   concatenated in cell order; ndof(pattern)/3 entries per cell */
+  const uint16_t* pattern;      /* host [n_cells]: pattern id (index into the uploaded library) */
+  const uint8_t* orient;        /* host [n_cells]: orientation code, see above */
+  const uint8_t* level;         /* host [n_cells]: octree level */
+  const uint8_t* material;      /* host [n_cells]: material id < n_materials */
+  int32_t n_materials;
+  const double* E;              /* host [n_materials]: Young's modulus relative to the library's */
+  const double* rho;            /* host [n_materials]: density */
+  const uint8_t* fixed_dof;     /* host [3N]: 1 = Dirichlet dof (held at zero), may be NULL */
+  int64_t load_nnz;             /* entries of the nodal load vector b (Gamma_N) */
+  const int64_t* load_dof;      /* host [load_nnz]: dof index */
+  const double* load_val;       /* host [load_nnz]: value; f_ext(t) = P(t) b */
+  int32_t load_kind;            /* sbfem_load_kind */
+  double load_t1, load_P0;      /* parameters t1 and P0 of P(t) */
+  int32_t load_cycles;          /* cycles of the sine burst */
+  double dt;                    /* time step (> 0) */
+  double alpha;                 /* mass-proportional damping C = alpha M (eq. C) */
+  int32_t prod;                 /* sbfem_prod */
+  int32_t state;                /* sbfem_state */
+  int32_t assembly;             /* sbfem_asm */
+  const double* u0;             /* host [3N] initial displacement, NULL = zero */
+  const double* v0;             /* host [3N] initial velocity, NULL = zero */
+} sbfem_mesh_desc;
+
+/*
+ * Upload the master-cell library (Table "Data structure": K_e and M_e of the
+ * unique patterns, unit edge, unit modulus and density, one Poisson ratio).
+ *   ndof      host [n_patterns]: 3 * nodes of each pattern (24..78)
+ *   K         host: row-major ndof x ndof blocks, concatenated in pattern order
+ *   m         host: lumped diagonal masses (ndof each), concatenated
+ *   omega     host [n_patterns]: largest circular frequency of K phi = w^2 m phi
+ * Fails with SBFEM_EINVAL for ndof outside 24..78 or not a multiple of 3, or a
+ * non-positive mass.
+ */
+sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, const int32_t* ndof,
+                                   const double* K, const double* m, const double* omega,
+                                   void* hip_stream);
+void sbfem_destroy_patterns(sbfem_patterns* p);
+
+/* Device bytes create_mesh would allocate for this descriptor (admission control). */
+sbfem_status sbfem_mesh_footprint(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t* bytes);
+
+/* Smallest element limit 2/omega_max,e over the cells (eqs. tcr, tcr_scale). */
+sbfem_status sbfem_critical_dt(const sbfem_patterns* p, const sbfem_mesh_desc* d, double* dt_cr);
+
+/*
+ * Build a resident simulation: validates the mesh (node ids in range, pattern
+ * ids in range, orientation < 48, material < n_materials, dt > 0, every free
+ * dof with positive lumped mass), sorts cells by pattern, assembles the lumped
+ * diagonal mass (Alg. 1 set-up), and sets u_0 and the start-up point
+ * u_-1 = u_0 - dt v_0 + dt^2/2 M^-1 (P(0) b - K u_0) - alpha dt^2/2 v_0 (eq. D0).
+ * The step counter starts at 0.
+ */
+sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const sbfem_mesh_desc* d,
+                               void* hip_stream);
+void sbfem_destroy_mesh(sbfem_mesh* m);
+
+/*
+ * Advance n_steps central-difference steps (Alg. 1 time loop):
+ *   R_int = sum_e s_e R_e^T K_p R_e u_e,  r = P(t_n) b - R_int,  t_n = n dt,
+ *   u_{n+1} = (dt^2 M^-1 r + 2 u_n - (1 - alpha dt/2) u_{n-1}) / (1 + alpha dt/2).
+ * Returns SBFEM_EUNSTABLE if the displacement became non-finite.
+ */
+sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream);
+
+/*
+ * Advance several meshes in one stream: mesh i takes n_steps[i] steps.  Steps
+ * of different meshes are interleaved so that each launch covers every mesh
+ * that still has steps to take.
+ */
+sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream);
+
+/*
+ * Copy state to host memory host_out [3N] (FP64):
+ *   which = 0: u_n, 1: u_{n-1}, 2: R_int(u_n) = sum_e s_e R_e^T K_p R_e u_e.
+ * *step (may be NULL) receives n.  Blocks until the copy has landed.
+ */
+sbfem_status sbfem_read_state(sbfem_mesh* m, int32_t which, double* host_out, int64_t* step,
+                              void* hip_stream);
+
+/* Replace u_n, u_{n-1} (host [3N] each) and the step counter (checkpoint restore). */
+sbfem_status sbfem_write_state(sbfem_mesh* m, const double* u_n, const double* u_nm1, int64_t step,
+                               void* hip_stream);
+
+/* Device bytes held by a mesh, and the number of cells per pattern-size class (diagnostics). */
+sbfem_status sbfem_mesh_info(const sbfem_mesh* m, int64_t* device_bytes, int64_t* n_dof, int32_t* n_colours);
+
+/* Last error message of the calling thread ("" if none). */
+const char* sbfem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBFEM_H */

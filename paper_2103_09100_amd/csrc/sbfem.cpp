@@ -1,0 +1,648 @@
+// C-ABI host implementation of the explicit octree-SBFEM stepper (see include/sbfem.h).
+//
+// Set-up (Alg. 1, initialisation): validate the mesh, optionally colour the
+// cells (no two cells of a colour share a node), sort cells by (colour,
+// pattern) into segments, lay the node ids of each segment out slot-major,
+// assemble the lumped diagonal mass and the start-up point (eq. D0), and upload
+// everything once.  Time loop: per step a load kernel, the element kernels of
+// each colour, and the central-difference update (eq. DnMdiag).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/sbfem.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sbfem_status fail(sbfem_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                     \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return hipSuccess;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// orientation code -> (pi, s), the same decoding as the device code
+void decode(int code, int pi[3], double s[3]) {
+  const int p = code >> 3;
+  pi[0] = p >> 1;
+  const int lo = (pi[0] == 0) ? 1 : 0;
+  const int hi = (pi[0] == 2) ? 1 : 2;
+  pi[1] = (p & 1) ? hi : lo;
+  pi[2] = (p & 1) ? lo : hi;
+  for (int a = 0; a < 3; ++a) s[a] = ((code >> a) & 1) ? -1.0 : 1.0;
+}
+
+double load_time_host(const sbfem::LoadParams& L, double t) {
+  if (L.kind == SBFEM_LOAD_RICKER) {
+    const double tau = (t - L.t1) / (L.t1 / 5.0);
+    return (1.0 - tau * tau) * std::exp(-0.5 * tau * tau) * L.P0;
+  }
+  if (L.kind == SBFEM_LOAD_TRIANGLE) {
+    if (t < 0.0 || t > 2.0 * L.t1) return 0.0;
+    return (1.0 - std::fabs(t / L.t1 - 1.0)) * L.P0;
+  }
+  if (t < 0.0 || t > L.t1) return 0.0;
+  const double pi = 3.14159265358979323846;
+  const double w = std::sin(pi * t / L.t1);
+  return std::sin(2.0 * pi * L.cycles * t / L.t1) * w * w * L.P0;
+}
+
+}  // namespace
+
+struct sbfem_patterns {
+  int32_t n = 0;
+  int device = 0;
+  std::vector<int32_t> ndof;
+  std::vector<int64_t> koff, moff;
+  std::vector<double> K, m, omega;
+  double* dK64 = nullptr;
+  float* dK32 = nullptr;
+};
+
+struct sbfem_mesh {
+  const sbfem_patterns* P = nullptr;
+  int device = 0;
+  int64_t N = 0, C = 0, ndof = 0;
+  double h0 = 1.0, dt = 0.0, alpha = 0.0;
+  int prod = 0, state_mode = 0, assembly = 0;
+  sbfem::LoadParams L{};
+  double* u = nullptr;
+  double* um1 = nullptr;
+  double* f = nullptr;
+  double* minv = nullptr;
+  double* matE = nullptr;
+  int32_t* conn = nullptr;
+  uint8_t* orient = nullptr;
+  uint8_t* level = nullptr;
+  uint8_t* material = nullptr;
+  sbfem::Tile* tiles = nullptr;
+  int64_t* load_idx = nullptr;
+  double* load_val = nullptr;
+  int64_t nnz = 0;
+  int32_t* flag_d = nullptr;
+  int32_t* flag_h = nullptr;
+  hipEvent_t flag_ev = nullptr;
+  bool flag_pending = false;
+  std::vector<sbfem::TileRange> groups;  // one per colour
+  int64_t step = 0;
+  int64_t bytes = 0;
+  int n_colours = 1;
+};
+
+namespace {
+
+sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
+  if (!p || !d) return fail(SBFEM_EINVAL, "null patterns or descriptor");
+  if (d->n_nodes <= 0 || d->n_cells <= 0) return fail(SBFEM_EINVAL, "empty mesh");
+  if (3 * d->n_nodes > (int64_t)INT32_MAX * 3) return fail(SBFEM_EINVAL, "too many nodes for int32 ids");
+  if (!d->conn || !d->pattern || !d->orient || !d->level || !d->material)
+    return fail(SBFEM_EINVAL, "missing cell arrays");
+  if (d->n_materials <= 0 || d->n_materials > 256 || !d->E || !d->rho)
+    return fail(SBFEM_EINVAL, "bad material table");
+  for (int i = 0; i < d->n_materials; ++i)
+    if (!(d->E[i] > 0) || !(d->rho[i] > 0)) return fail(SBFEM_EINVAL, "material %d: E and rho must be > 0", i);
+  if (!(d->h0 > 0)) return fail(SBFEM_EINVAL, "h0 must be > 0");
+  if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(SBFEM_EINVAL, "dt must be > 0");
+  if (d->load_nnz < 0 || (d->load_nnz > 0 && (!d->load_dof || !d->load_val)))
+    return fail(SBFEM_EINVAL, "bad load vector");
+  if (d->load_kind < 0 || d->load_kind > 2) return fail(SBFEM_EINVAL, "unknown load kind");
+  if (d->prod != SBFEM_PROD_FP64 && d->prod != SBFEM_PROD_FP32)
+    return fail(SBFEM_EINVAL, "product precision %d not available", d->prod);
+  if (d->state != SBFEM_STATE_FP64) return fail(SBFEM_EINVAL, "state storage %d not available", d->state);
+  if (d->assembly != SBFEM_ASM_ATOMIC && d->assembly != SBFEM_ASM_COLOUR)
+    return fail(SBFEM_EINVAL, "unknown assembly mode");
+  for (int64_t c = 0; c < d->n_cells; ++c) {
+    if (d->pattern[c] >= p->n) return fail(SBFEM_EINVAL, "cell %lld: pattern %d out of range", (long long)c, d->pattern[c]);
+    if (d->orient[c] >= 48) return fail(SBFEM_EINVAL, "cell %lld: orientation %d >= 48", (long long)c, d->orient[c]);
+    if (d->material[c] >= d->n_materials) return fail(SBFEM_EINVAL, "cell %lld: material out of range", (long long)c);
+    if (d->level[c] > 40) return fail(SBFEM_EINVAL, "cell %lld: level %d too deep", (long long)c, d->level[c]);
+  }
+  return SBFEM_OK;
+}
+
+int64_t footprint_bytes(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t total_conn) {
+  const int64_t ndof = 3 * d->n_nodes;
+  int64_t b = ndof * 8 * 4;                     // u, u_prev, f, minv
+  b += total_conn * 4 + d->n_cells * 3;         // node ids, orientation, level, material
+  b += ((d->n_cells + sbfem::kTile - 1) / sbfem::kTile + p->n * 64) * (int64_t)sizeof(sbfem::Tile);
+  b += d->load_nnz * 16 + 256 * 8 + 64;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sbfem_last_error(void) { return g_err.c_str(); }
+
+sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, const int32_t* ndof,
+                                   const double* K, const double* m, const double* omega, void* hip_stream) {
+  if (!out) return fail(SBFEM_EINVAL, "null output handle");
+  *out = nullptr;
+  if (n_patterns <= 0 || n_patterns > 65535 || !ndof || !K || !m || !omega)
+    return fail(SBFEM_EINVAL, "bad pattern library arguments");
+  auto* p = new sbfem_patterns();
+  p->n = n_patterns;
+  int64_t ko = 0, mo = 0;
+  for (int i = 0; i < n_patterns; ++i) {
+    if (ndof[i] < 24 || ndof[i] > 78 || ndof[i] % 3) {
+      delete p;
+      return fail(SBFEM_EINVAL, "pattern %d: ndof %d not in 24..78 or not a multiple of 3", i, ndof[i]);
+    }
+    p->ndof.push_back(ndof[i]);
+    p->koff.push_back(ko);
+    p->moff.push_back(mo);
+    ko += (int64_t)ndof[i] * ndof[i];
+    mo += ndof[i];
+  }
+  p->K.assign(K, K + ko);
+  p->m.assign(m, m + mo);
+  p->omega.assign(omega, omega + n_patterns);
+  for (int64_t i = 0; i < mo; ++i)
+    if (!(p->m[i] > 0)) {
+      delete p;
+      return fail(SBFEM_EINVAL, "non-positive lumped mass in the library");
+    }
+  for (int i = 0; i < n_patterns; ++i)
+    if (!(p->omega[i] > 0)) {
+      delete p;
+      return fail(SBFEM_EINVAL, "pattern %d: non-positive frequency", i);
+    }
+  std::vector<float> K32(p->K.begin(), p->K.end());
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = dalloc(&p->dK64, ko);
+  if (e == hipSuccess) e = dalloc(&p->dK32, ko);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->dK64, p->K.data(), ko * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->dK32, K32.data(), ko * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    dfree(p->dK64);
+    dfree(p->dK32);
+    delete p;
+    return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "pattern upload: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return SBFEM_OK;
+}
+
+void sbfem_destroy_patterns(sbfem_patterns* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  dfree(p->dK64);
+  dfree(p->dK32);
+  delete p;
+}
+
+sbfem_status sbfem_mesh_footprint(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t* bytes) {
+  if (!p || !d || !bytes) return fail(SBFEM_EINVAL, "null argument");
+  int64_t tc = 0;
+  for (int64_t c = 0; c < d->n_cells; ++c) {
+    if (d->pattern[c] >= p->n) return fail(SBFEM_EINVAL, "pattern out of range");
+    tc += p->ndof[d->pattern[c]] / 3;
+  }
+  *bytes = footprint_bytes(p, d, tc);
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_critical_dt(const sbfem_patterns* p, const sbfem_mesh_desc* d, double* dt_cr) {
+  if (!dt_cr) return fail(SBFEM_EINVAL, "null output");
+  sbfem_status st = validate_desc(p, d);
+  if (st != SBFEM_OK && st != SBFEM_EINVAL) return st;
+  if (!p || !d || d->n_cells <= 0) return fail(SBFEM_EINVAL, "empty mesh");
+  double best = INFINITY;
+  for (int64_t c = 0; c < d->n_cells; ++c) {
+    const int pid = d->pattern[c];
+    if (pid >= p->n || d->material[c] >= d->n_materials) return fail(SBFEM_EINVAL, "cell %lld out of range", (long long)c);
+    const double h = std::ldexp(d->h0, -(int)d->level[c]);
+    const double w = p->omega[pid] * std::sqrt(d->E[d->material[c]] / d->rho[d->material[c]]) / h;
+    best = std::min(best, 2.0 / w);
+  }
+  *dt_cr = best;
+  return SBFEM_OK;
+}
+
+void sbfem_destroy_mesh(sbfem_mesh* m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  if (m->flag_ev) (void)hipEventDestroy(m->flag_ev);
+  if (m->flag_h) (void)hipHostFree(m->flag_h);
+  dfree(m->u);
+  dfree(m->um1);
+  dfree(m->f);
+  dfree(m->minv);
+  dfree(m->matE);
+  dfree(m->conn);
+  dfree(m->orient);
+  dfree(m->level);
+  dfree(m->material);
+  dfree(m->tiles);
+  dfree(m->load_idx);
+  dfree(m->load_val);
+  dfree(m->flag_d);
+  delete m;
+}
+
+static sbfem::ElementArgs element_args(const sbfem_mesh* m) {
+  sbfem::ElementArgs a;
+  a.tiles = m->tiles;
+  a.u = m->u;
+  a.f = m->f;
+  a.conn = m->conn;
+  a.orient = m->orient;
+  a.level = m->level;
+  a.material = m->material;
+  a.matE = m->matE;
+  a.h0 = m->h0;
+  a.K64 = m->P->dK64;
+  a.K32 = m->P->dK32;
+  return a;
+}
+
+// f += R_int(u) over all colours (f must hold what it should be added to)
+static sbfem_status internal_force(sbfem_mesh* m, hipStream_t s) {
+  sbfem::ElementArgs a = element_args(m);
+  const bool atomic = m->assembly == SBFEM_ASM_ATOMIC;
+  for (const auto& g : m->groups) HIP_TRY(sbfem::launch_ebe(a, g, m->prod == SBFEM_PROD_FP32, atomic, s));
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const sbfem_mesh_desc* d,
+                               void* hip_stream) {
+  if (!out) return fail(SBFEM_EINVAL, "null output handle");
+  *out = nullptr;
+  sbfem_status st = validate_desc(p, d);
+  if (st != SBFEM_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t N = d->n_nodes, C = d->n_cells, ndof = 3 * N;
+
+  // per-cell node counts and offsets into conn (input order)
+  std::vector<int64_t> cptr(C + 1, 0);
+  for (int64_t c = 0; c < C; ++c) cptr[c + 1] = cptr[c] + p->ndof[d->pattern[c]] / 3;
+  const int64_t total = cptr[C];
+  for (int64_t i = 0; i < total; ++i)
+    if (d->conn[i] < 0 || d->conn[i] >= N)
+      return fail(SBFEM_EINVAL, "node id %d at conn[%lld] out of range", d->conn[i], (long long)i);
+
+  // colours: greedy in input order, per-node mask of the colours already touching it
+  std::vector<uint8_t> colour(C, 0);
+  int n_colours = 1;
+  if (d->assembly == SBFEM_ASM_COLOUR) {
+    std::vector<uint64_t> used(N, 0);
+    for (int64_t c = 0; c < C; ++c) {
+      uint64_t forb = 0;
+      for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) forb |= used[d->conn[i]];
+      if (forb == ~0ull) return fail(SBFEM_EINVAL, "cell %lld needs more than 64 colours", (long long)c);
+      int col = 0;
+      while ((forb >> col) & 1) ++col;
+      colour[c] = (uint8_t)col;
+      n_colours = std::max(n_colours, col + 1);
+      for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) used[d->conn[i]] |= 1ull << col;
+    }
+  }
+
+  // order: colour, 8-node class first, pattern; stable in input order (counting sort)
+  const int64_t n_keys = (int64_t)n_colours * 2 * p->n;
+  auto key = [&](int64_t c) -> int64_t {
+    const int pid = d->pattern[c];
+    const int mixed = p->ndof[pid] == 24 ? 0 : 1;
+    return ((int64_t)colour[c] * 2 + mixed) * p->n + pid;
+  };
+  std::vector<int64_t> order(C);
+  {
+    std::vector<int64_t> start(n_keys + 1, 0);
+    for (int64_t c = 0; c < C; ++c) start[key(c) + 1]++;
+    for (int64_t k = 0; k < n_keys; ++k) start[k + 1] += start[k];
+    for (int64_t c = 0; c < C; ++c) order[start[key(c)]++] = c;
+  }
+
+  auto* m = new sbfem_mesh();
+  m->P = p;
+  (void)hipGetDevice(&m->device);
+  m->N = N;
+  m->C = C;
+  m->ndof = ndof;
+  m->h0 = d->h0;
+  m->dt = d->dt;
+  m->alpha = d->alpha;
+  m->prod = d->prod;
+  m->state_mode = d->state;
+  m->assembly = d->assembly;
+  m->L.kind = d->load_kind;
+  m->L.cycles = d->load_cycles;
+  m->L.t1 = d->load_t1;
+  m->L.P0 = d->load_P0;
+  m->n_colours = n_colours;
+
+  // segments, tiles and slot-major node ids
+  std::vector<int32_t> sconn(total);
+  std::vector<uint8_t> sorient(C), slevel(C), smat(C);
+  std::vector<sbfem::Tile> tiles;
+  m->groups.assign(n_colours, sbfem::TileRange{0, 0, 0});
+  int64_t cpos = 0, i0 = 0;
+  for (int col = 0; col < n_colours; ++col) m->groups[col].first = -1;
+  while (i0 < C) {
+    int64_t i1 = i0;
+    const int64_t k0 = key(order[i0]);
+    while (i1 < C && key(order[i1]) == k0) ++i1;
+    const int pid = d->pattern[order[i0]];
+    const int nn = p->ndof[pid] / 3;
+    const int col = colour[order[i0]];
+    const int64_t cnt = i1 - i0;
+    for (int64_t j = 0; j < cnt; ++j) {
+      const int64_t c = order[i0 + j];
+      for (int k = 0; k < nn; ++k) sconn[cpos + (int64_t)k * cnt + j] = d->conn[cptr[c] + k];
+      sorient[i0 + j] = d->orient[c];
+      slevel[i0 + j] = d->level[c];
+      smat[i0 + j] = d->material[c];
+    }
+    auto& g = m->groups[col];
+    if (g.first < 0) g.first = (int64_t)tiles.size();
+    for (int64_t j = 0; j < cnt; j += sbfem::kTile) {
+      sbfem::Tile t;
+      t.cell0 = i0 + j;
+      t.conn0 = cpos + j;
+      t.stride = cnt;
+      t.koff = p->koff[pid];
+      t.count = (int32_t)std::min<int64_t>(sbfem::kTile, cnt - j);
+      t.nn = nn;
+      tiles.push_back(t);
+      if (nn == 8)
+        g.n_fixed8++;
+      else
+        g.n_mixed++;
+    }
+    cpos += cnt * nn;
+    i0 = i1;
+  }
+  for (auto& g : m->groups)
+    if (g.first < 0) g.first = 0;
+
+  // lumped diagonal mass (input order; summation order fixed)
+  std::vector<double> mdiag(ndof, 0.0);
+  for (int64_t c = 0; c < C; ++c) {
+    const int pid = d->pattern[c];
+    const double h = std::ldexp(d->h0, -(int)d->level[c]);
+    const double sc = d->rho[d->material[c]] * h * h * h;
+    int pi[3];
+    double sg[3];
+    decode(d->orient[c], pi, sg);
+    const double* mp = p->m.data() + p->moff[pid];
+    for (int64_t k = 0; k < cptr[c + 1] - cptr[c]; ++k)
+      for (int a = 0; a < 3; ++a) mdiag[3 * (int64_t)d->conn[cptr[c] + k] + pi[a]] += sc * mp[3 * k + a];
+  }
+  std::vector<double> minv(ndof);
+  for (int64_t i = 0; i < ndof; ++i) {
+    const bool fixed = d->fixed_dof && d->fixed_dof[i];
+    if (fixed) {
+      minv[i] = 0.0;
+    } else {
+      if (!(mdiag[i] > 0)) {
+        sbfem_destroy_mesh(m);
+        return fail(SBFEM_EINVAL, "free dof %lld has no mass (node not used by any cell?)", (long long)i);
+      }
+      minv[i] = 1.0 / mdiag[i];
+    }
+  }
+
+  // load vector with merged duplicates
+  std::map<int64_t, double> bmap;
+  for (int64_t i = 0; i < d->load_nnz; ++i) {
+    if (d->load_dof[i] < 0 || d->load_dof[i] >= ndof) {
+      sbfem_destroy_mesh(m);
+      return fail(SBFEM_EINVAL, "load dof %lld out of range", (long long)d->load_dof[i]);
+    }
+    bmap[d->load_dof[i]] += d->load_val[i];
+  }
+  std::vector<int64_t> bidx;
+  std::vector<double> bval;
+  for (auto& kv : bmap) {
+    bidx.push_back(kv.first);
+    bval.push_back(kv.second);
+  }
+  m->nnz = (int64_t)bidx.size();
+
+  std::vector<double> matE(256, 0.0);
+  for (int i = 0; i < d->n_materials; ++i) matE[i] = d->E[i];
+
+  m->bytes = footprint_bytes(p, d, total);
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, n)                                      \
+  if (e == hipSuccess) e = dalloc(&m->ptr, (size_t)(n));
+  ALLOC(u, ndof)
+  ALLOC(um1, ndof)
+  ALLOC(f, ndof)
+  ALLOC(minv, ndof)
+  ALLOC(matE, 256)
+  ALLOC(conn, total)
+  ALLOC(orient, C)
+  ALLOC(level, C)
+  ALLOC(material, C)
+  ALLOC(tiles, tiles.size())
+  ALLOC(load_idx, m->nnz)
+  ALLOC(load_val, m->nnz)
+  ALLOC(flag_d, 1)
+#undef ALLOC
+  if (e == hipSuccess) e = hipHostMalloc((void**)&m->flag_h, sizeof(int32_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->flag_ev, hipEventDisableTiming);
+  auto H2D = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  H2D(m->minv, minv.data(), ndof * 8);
+  H2D(m->matE, matE.data(), 256 * 8);
+  H2D(m->conn, sconn.data(), total * 4);
+  H2D(m->orient, sorient.data(), C);
+  H2D(m->level, slevel.data(), C);
+  H2D(m->material, smat.data(), C);
+  H2D(m->tiles, tiles.data(), tiles.size() * sizeof(sbfem::Tile));
+  H2D(m->load_idx, bidx.data(), m->nnz * 8);
+  H2D(m->load_val, bval.data(), m->nnz * 8);
+  if (e == hipSuccess) e = hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s);
+  if (e == hipSuccess) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
+  if (e != hipSuccess) {
+    sbfem_destroy_mesh(m);
+    return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "create_mesh upload: %s",
+                hipGetErrorString(e));
+  }
+  *m->flag_h = 0;
+
+  // start-up point (eq. D0): u_-1 = u0 - dt v0 + dt^2/2 a0,  a0 = M^-1 (P(0) b - K u0) - alpha v0
+  std::vector<double> u0(ndof, 0.0), v0(ndof, 0.0), ku0(ndof, 0.0);
+  if (d->u0) std::copy(d->u0, d->u0 + ndof, u0.begin());
+  if (d->v0) std::copy(d->v0, d->v0 + ndof, v0.begin());
+  for (int64_t i = 0; i < ndof; ++i)
+    if (minv[i] == 0.0) u0[i] = v0[i] = 0.0;
+  H2D(m->u, u0.data(), ndof * 8);
+  if (e == hipSuccess && d->u0) {
+    sbfem_status fs = internal_force(m, s);
+    if (fs != SBFEM_OK) {
+      sbfem_destroy_mesh(m);
+      return fs;
+    }
+    e = hipMemcpyAsync(ku0.data(), m->f, ndof * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
+  }
+  const double P0t = load_time_host(m->L, 0.0);
+  std::vector<double> um1(ndof);
+  std::vector<double> fext(ndof, 0.0);
+  for (size_t i = 0; i < bidx.size(); ++i) fext[bidx[i]] = P0t * bval[i];
+  for (int64_t i = 0; i < ndof; ++i) {
+    const double a0 = minv[i] * (fext[i] - ku0[i]) - (minv[i] != 0.0 ? d->alpha * v0[i] : 0.0);
+    um1[i] = u0[i] - d->dt * v0[i] + 0.5 * d->dt * d->dt * a0;
+  }
+  H2D(m->um1, um1.data(), ndof * 8);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    sbfem_destroy_mesh(m);
+    return fail(SBFEM_EDEVICE, "create_mesh initial state: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return SBFEM_OK;
+}
+
+static sbfem_status check_flag(sbfem_mesh* m) {
+  if (!m->flag_pending) return SBFEM_OK;
+  hipError_t q = hipEventQuery(m->flag_ev);
+  if (q == hipErrorNotReady) return SBFEM_OK;
+  m->flag_pending = false;
+  if (q != hipSuccess) return fail(SBFEM_EDEVICE, "finite check: %s", hipGetErrorString(q));
+  if (*m->flag_h) return fail(SBFEM_EUNSTABLE, "displacement became non-finite (time step above the stability limit?)");
+  return SBFEM_OK;
+}
+
+static sbfem_status enqueue_step(sbfem_mesh* m, hipStream_t s) {
+  const double t = (double)m->step * m->dt;
+  HIP_TRY(sbfem::launch_load(m->f, m->load_idx, m->load_val, m->nnz, m->L, t, s));
+  sbfem_status st = internal_force(m, s);
+  if (st != SBFEM_OK) return st;
+  HIP_TRY(sbfem::launch_update(m->u, m->um1, m->f, m->minv, m->ndof, m->dt * m->dt, 0.5 * m->alpha * m->dt, s));
+  std::swap(m->u, m->um1);
+  m->step++;
+  return SBFEM_OK;
+}
+
+static sbfem_status finish_steps(sbfem_mesh* m, hipStream_t s) {
+  HIP_TRY(sbfem::launch_finite(m->u, m->ndof, m->flag_d, s));
+  HIP_TRY(hipMemcpyAsync(m->flag_h, m->flag_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(m->flag_ev, s));
+  m->flag_pending = true;
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream) {
+  if (!m) return fail(SBFEM_EINVAL, "null mesh");
+  if (n_steps < 0) return fail(SBFEM_EINVAL, "negative step count");
+  HIP_TRY(hipSetDevice(m->device));
+  sbfem_status st = check_flag(m);
+  if (st != SBFEM_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    st = enqueue_step(m, s);
+    if (st != SBFEM_OK) return st;
+  }
+  if (n_steps > 0) return finish_steps(m, s);
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!ms || !n_steps))) return fail(SBFEM_EINVAL, "bad batch arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  int64_t most = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ms[i] || n_steps[i] < 0) return fail(SBFEM_EINVAL, "bad batch entry %d", i);
+    sbfem_status st = check_flag(ms[i]);
+    if (st != SBFEM_OK) return st;
+    most = std::max(most, n_steps[i]);
+  }
+  for (int64_t k = 0; k < most; ++k)
+    for (int i = 0; i < n; ++i)
+      if (k < n_steps[i]) {
+        sbfem_status st = enqueue_step(ms[i], s);
+        if (st != SBFEM_OK) return st;
+      }
+  for (int i = 0; i < n; ++i)
+    if (n_steps[i] > 0) {
+      sbfem_status st = finish_steps(ms[i], s);
+      if (st != SBFEM_OK) return st;
+    }
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_read_state(sbfem_mesh* m, int32_t which, double* host_out, int64_t* step, void* hip_stream) {
+  if (!m || !host_out) return fail(SBFEM_EINVAL, "null argument");
+  if (which < 0 || which > 2) return fail(SBFEM_EINVAL, "which must be 0, 1 or 2");
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (which == 2) {
+    sbfem_status st = internal_force(m, s);
+    if (st != SBFEM_OK) return st;
+    HIP_TRY(hipMemcpyAsync(host_out, m->f, m->ndof * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(sbfem::launch_fill(m->f, m->ndof, 0.0, s));
+  } else {
+    HIP_TRY(hipMemcpyAsync(host_out, which == 0 ? m->u : m->um1, m->ndof * 8, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (step) *step = m->step;
+  return check_flag(m);
+}
+
+sbfem_status sbfem_write_state(sbfem_mesh* m, const double* u_n, const double* u_nm1, int64_t step,
+                               void* hip_stream) {
+  if (!m || !u_n || !u_nm1) return fail(SBFEM_EINVAL, "null argument");
+  if (step < 0) return fail(SBFEM_EINVAL, "negative step");
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipMemcpyAsync(m->u, u_n, m->ndof * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(m->um1, u_nm1, m->ndof * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  m->step = step;
+  m->flag_pending = false;
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_mesh_info(const sbfem_mesh* m, int64_t* device_bytes, int64_t* n_dof, int32_t* n_colours) {
+  if (!m) return fail(SBFEM_EINVAL, "null mesh");
+  if (device_bytes) *device_bytes = m->bytes;
+  if (n_dof) *n_dof = m->ndof;
+  if (n_colours) *n_colours = m->n_colours;
+  return SBFEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (max relative displacement error over the sampled steps, the
+oracle's e_max):
+  * FP64 products and state: 1e-9 (both sides sum in different orders; the
+    two libraries of master cells agree to 1e-14);
+  * FP32 products with FP64 state: 1e-5 (the target for the mixed path).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from meshgen import configs
+from oracle.solver import Oracle, relative_error
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+FP32_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim_mod():
+    from paper_2103_09100_amd import solver
+    return solver
+
+
+@pytest.fixture(scope="module")
+def cfg1_ref():
+    m = configs.cfg1()
+    o = Oracle(m)
+    return m, o.run()
+
+
+@pytest.mark.parametrize("assembly", ["atomic", "colour"])
+def test_cfg1_fp64(sim_mod, cfg1_ref, assembly):
+    m, ref = cfg1_ref
+    _say(f"[cfg1 fp64 {assembly}]")
+    s = sim_mod.Simulation(m, assembly=assembly)
+    assert abs(s.dt - ref["dt"]) <= 1e-14 * ref["dt"]
+    snaps = s.run(1000, 50)
+    e = relative_error(snaps, ref["snapshots"])
+    _say(f"  e_max = {e:.3e}")
+    assert e <= FP64_TOL
+
+
+def test_cfg1_colour_bitwise_reproducible(sim_mod):
+    m = configs.cfg1()
+    a = sim_mod.Simulation(m, assembly="colour")
+    b = sim_mod.Simulation(m, assembly="colour")
+    a.step(300)
+    b.step(120)
+    b.step(180)
+    assert np.array_equal(a.u(), b.u())
+
+
+@pytest.fixture(scope="module")
+def zoo_ref():
+    m = configs.small_zoo(n_steps=200)
+    o = Oracle(m, workers=8)
+    return m, o, o.run(n_steps=200)
+
+
+@pytest.mark.parametrize("prod,assembly,tol", [("fp64", "atomic", FP64_TOL), ("fp64", "colour", FP64_TOL),
+                                                ("fp32", "atomic", FP32_TOL)])
+def test_all_patterns(sim_mod, zoo_ref, prod, assembly, tol):
+    m, o, ref = zoo_ref
+    _say(f"[all-pattern mesh {m.n_dof} dofs, {prod} {assembly}]")
+    s = sim_mod.Simulation(m, prod=prod, assembly=assembly, orient_seed=3)
+    snaps = s.run(200, 50)
+    e = relative_error(snaps, ref["snapshots"])
+    _say(f"  e_max = {e:.3e}")
+    assert e <= tol
+
+
+def test_internal_force_elementwise(sim_mod, zoo_ref):
+    m, o, _ = zoo_ref
+    u, um1 = configs.random_state(m.n_dof, seed=1, fixed=m.fixed)
+    s = sim_mod.Simulation(m, assembly="colour", orient_seed=5)
+    s.write(u, um1, 0)
+    f_gpu = s.internal_force()
+    f_ref = o.internal_force(u)
+    err = np.abs(f_gpu - f_ref).max() / np.abs(f_ref).max()
+    _say(f"[R_int elementwise] {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_cfg2_full_size_one_step_sampled(sim_mod):
+    m = configs.cfg2()
+    _say(f"[cfg2 one step, {m.n_dof} dofs]")
+    o = Oracle(m, workers=8)
+    dt = 0.5 * o.critical_dt()
+    u, um1 = configs.random_state(m.n_dof, seed=2, fixed=m.fixed)
+    s = sim_mod.Simulation(m, dt=dt, assembly="atomic", orient_seed=1)
+    s.write(u, um1, 37)
+    s.step(1)
+    got = s.u().reshape(-1, 3)
+    nodes = np.random.default_rng(3).choice(m.n_nodes, 400, replace=False)
+    # include nodes of every kind of cell
+    nodes = np.unique(np.concatenate([nodes, m.conn[m.conn_ptr[np.flatnonzero(m.cell_slots)[:200]]]]))
+    want = o.sampled_step(u, um1, 37, dt, nodes)
+    err = np.abs(got[nodes] - want).max() / np.abs(want).max()
+    _say(f"  sampled one-step error {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_checkpoint_resume(sim_mod):
+    m = configs.cfg1()
+    a = sim_mod.Simulation(m, assembly="colour")
+    a.step(200)
+    u, um1, n = a.state()
+    b = sim_mod.Simulation(m, assembly="colour")
+    b.write(u, um1, n)
+    a.step(150)
+    b.step(150)
+    assert np.array_equal(a.u(), b.u())
+
+
+def test_single_cell_and_ragged_tiles(sim_mod):
+    # one root cube: a single 8-node cell, base fixed, point load on a top corner
+    from meshgen.octree import build_mesh
+    m = build_mesh((1, 1, 1), 1.0, 0, 0, lambda l, i: np.zeros(len(i), bool), nu=0.25,
+                   fixed=lambda lat, lmax: np.repeat((lat[:, 2] == 0)[:, None], 3, axis=1))
+    configs.point_load(m, (1.0, 1.0, 1.0), (0, 0, -1.0))
+    configs._run_params(m, fm=2.0, n_steps=100)
+    o = Oracle(m)
+    ref = o.run(n_steps=100)
+    s = sim_mod.Simulation(m)
+    e = relative_error(s.run(100, 50), ref["snapshots"])
+    _say(f"[single cell] {e:.3e}")
+    assert e <= FP64_TOL
+    # 257 cells in one pattern -> one full and one ragged tile
+    m = build_mesh((257, 1, 1), 1.0, 0, 0, lambda l, i: np.zeros(len(i), bool), nu=0.25,
+                   fixed=lambda lat, lmax: np.repeat((lat[:, 0] == 0)[:, None], 3, axis=1))
+    configs.patch_load(m, (0, 1), (0.5, 0.5), 1.0, pressure=-1.0)
+    configs._run_params(m, fm=0.05, n_steps=100)
+    o = Oracle(m)
+    ref = o.run(n_steps=100)
+    s = sim_mod.Simulation(m, assembly="colour")
+    e = relative_error(s.run(100, 50), ref["snapshots"])
+    _say(f"[257-cell bar] {e:.3e}")
+    assert e <= FP64_TOL
+
+
+def test_unstable_step_reported(sim_mod):
+    from paper_2103_09100_amd import binding
+    m = configs.cfg1()
+    s = sim_mod.Simulation(m)
+    s2 = sim_mod.Simulation(m, dt=3.0 * s.dt_cr)
+    with pytest.raises(binding.SbfemError) as ei:
+        s2.step(2000)
+        s2.u()
+    assert ei.value.status == binding.EUNSTABLE
+
+
+def test_invalid_mesh_rejected(sim_mod):
+    from paper_2103_09100_amd import binding, library
+    m = configs.cfg1()
+    pats = sim_mod.device_patterns(m.nu)
+    pid, code, conn = library.canonicalise(m)
+    bad = conn.copy()
+    bad[5] = m.n_nodes
+    d, keep = binding.make_desc(m, pid, code, bad, dt=0.01)
+    with pytest.raises(binding.SbfemError) as ei:
+        binding.Mesh(pats, d, keep)
+    assert ei.value.status == binding.EINVAL
+    p2 = pid.copy()
+    p2[0] = 500
+    d, keep = binding.make_desc(m, p2, code, conn, dt=0.01)
+    with pytest.raises(binding.SbfemError):
+        binding.Mesh(pats, d, keep)
