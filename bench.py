@@ -1,0 +1,213 @@
+"""Benchmark of the explicit octree-SBFEM hot path on one MI355X.
+
+Workload (default): one GPU's share of a paper-scale run -- a unit box with
+three random ellipsoidal inclusions (E ratio 5, rho ratio 2), octree levels
+8/9, ~3.0e8 dofs in ~9.9e7 cells, Ricker patch load, base fixed.  A step is
+one pass of the whole hot path: load, element-by-element internal force of
+every cell, central-difference update of every dof.
+
+Timed: K steps after W warm-up steps, bracketed by torch.cuda.synchronize(),
+with HIP events on the stream the library launches on.  The headline value
+is the FP32-product / FP64-state path; the plain FP64 path (and the colour
+assembly) are timed beside it.  A second, event-instrumented pass gives the
+average duration per launch of each kernel class for the roofline figure.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg3|cfg2]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-steps/s vs FP64 plain at ≤1e-5 rel err; % HBM roofline; p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(mesh, pid_nodes):
+    """Bytes the method must move per step (see the measurement notes):
+    per dof u_n, u_{n-1}, M^-1 read and u_{n+1} written (8 B each); per cell
+    its node ids (4 B each) and orientation, level, material (1 B each);
+    per load entry index + value."""
+    n_dof = mesh.n_dof
+    conn_bytes = 4 * int(mesh.conn.shape[0])
+    cell_bytes = 3 * mesh.n_cells
+    step = 32 * n_dof + conn_bytes + cell_bytes + 16 * len(mesh.load_dof)
+    # the 8-node element kernel: its cells' ids and metadata, and u_n of the nodes it reads
+    is8 = pid_nodes == 8
+    c8 = int(is8.sum())
+    mark = np.zeros(mesh.n_nodes, dtype=bool)
+    ptr = mesh.conn_ptr
+    cells8 = np.flatnonzero(is8)
+    # 8-node cells have 8 consecutive entries
+    idx = (ptr[cells8][:, None] + np.arange(8)[None, :]).ravel()
+    mark[mesh.conn[idx]] = True
+    nodes8 = int(mark.sum())
+    ebe8 = c8 * (4 * 8 + 3) + 24 * nodes8
+    update = 32 * n_dof
+    return dict(step=step, element_8node=ebe8, update=update, cells_8node=c8, nodes_8node=nodes8)
+
+
+def make_mesh(name):
+    from meshgen import configs
+    if name == "cfg3":
+        return configs.cfg3(keep_node_lat=True), "ellipsoid-inclusion octree L8/9 (one GPU's share of a paper-scale run)"
+    if name == "cfg2":
+        return configs.cfg2(), "sphere-band octree L3/7 with every cell pattern"
+    if name == "cfg4":
+        return configs.cfg4(), "sphere-band octree L4/8"
+    raise SystemExit(f"unknown config {name}")
+
+
+def time_mode(sim, torch, stream, steps, warmup):
+    with torch.cuda.stream(stream):
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def profile_mode(sim, torch, stream, steps):
+    sim.gpu.profile(True)
+    with torch.cuda.stream(stream):
+        sim.step(steps)
+        torch.cuda.synchronize()
+    prof = sim.gpu.profile_read()
+    sim.gpu.profile(False)
+    return {k: dict(ms_total=v[0], launches=v[1], ms_avg=(v[0] / v[1] if v[1] else 0.0)) for k, v in prof.items()}
+
+
+def cpu_baseline(seconds=12.0):
+    """The oracle (as it stands) on a bounded sample of the same recipe at levels 5/6."""
+    from threadpoolctl import threadpool_info
+    from meshgen import configs
+    from oracle.solver import Oracle
+    m = configs.inclusion_mesh(seed=0, lcoarse=5, lfine=6)
+    configs._run_params(m, fm=4.0, n_steps=200)
+    o = Oracle(m, workers=min(16, os.cpu_count() or 1))
+    dt = 0.5 * o.critical_dt()
+    u, um1 = o.initial_state(dt)
+    t0 = time.perf_counter()
+    n = 0
+    while n < 3 or time.perf_counter() - t0 < seconds:
+        unew, _ = o.step(u, um1, n, dt)
+        um1, u = u, unew
+        n += 1
+    el = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return dict(value=m.n_dof * n / el, unit="DOF-steps/s", cores=int(threads), kind="oracle",
+                sample=f"oracle step loop, same recipe at octree levels 5/6 ({m.n_dof} dofs, {m.n_cells} cells), "
+                       f"{n} steps in {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="cfg3")
+    ap.add_argument("--modes", default="fp32:tiled,fp64:tiled")
+    ap.add_argument("--compare", default="fp32:atomic,fp32:colour",
+                    help="assembly variants timed beside the headline over --compare-steps steps")
+    ap.add_argument("--compare-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"path is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2103_09100_amd import library
+    from paper_2103_09100_amd.solver import Simulation
+
+    t0 = time.time()
+    mesh, desc = make_mesh(args.config)
+    log(f"[bench] mesh {args.config}: {mesh.n_cells} cells, {mesh.n_nodes} nodes, {mesh.n_dof} dofs "
+        f"({time.time() - t0:.0f} s)")
+    pid, _, _ = library.canonicalise(mesh)
+    nn = library.pt.table().n_nodes[pid]
+    ab = algorithmic_bytes(mesh, nn)
+    del pid
+    log(f"[bench] algorithmic bytes/step {ab['step'] / 1e9:.3f} GB ({ab['step'] / mesh.n_dof:.1f} B/dof)")
+
+    stream = torch.cuda.Stream()
+    results = {}
+    finals = {}
+    plan = [(m, args.steps, args.warmup) for m in args.modes.split(",") if m]
+    plan += [(m, args.compare_steps, 2) for m in args.compare.split(",") if m]
+    for mode, n_steps, n_warm in plan:
+        prod, assembly = mode.split(":")
+        t1 = time.time()
+        sim = Simulation(mesh, prod=prod, assembly=assembly, stream=stream.cuda_stream)
+        log(f"[bench] {mode}: created in {time.time() - t1:.0f} s, dt={sim.dt:.4e}, "
+            f"{sim.gpu.info()['n_colours']} colours, {sim.footprint / 1e9:.1f} GB")
+        ms = time_mode(sim, torch, stream, n_steps, n_warm)
+        prof = profile_mode(sim, torch, stream, n_steps)
+        finals[mode] = sim.u()
+        results[mode] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), kernels=prof, steps=n_steps)
+        log(f"[bench] {mode}: {ms:.3f} ms/step, {results[mode]['value']:.3e} DOF-steps/s, "
+            + ", ".join(f"{k} {v['ms_avg']:.3f} ms x{v['launches']}" for k, v in prof.items()))
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
+    head = args.modes.split(",")[0]
+    fp64 = next((m for m in args.modes.split(",") if m.startswith("fp64:")), None)
+    r = results[head]
+    k8 = r["kernels"]["element_8node"]
+    achieved = ab["element_8node"] / (k8["ms_avg"] * 1e-3) / 1e9 if k8["ms_avg"] > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {desc}", "n_dof": mesh.n_dof, "n_cells": mesh.n_cells,
+                   "product": head.split(":")[0], "state": "fp64", "assembly": head.split(":")[1],
+                   "steps_per_call": args.steps},
+        "roofline": {"bound": "hbm", "kernel": "element kernel, 8-node cells", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "step_achieved": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9,
+                     "step_frac": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "alg_bytes_per_launch": ab["element_8node"], "alg_bytes_per_step": ab["step"],
+                     "avg_launch_ms": k8["ms_avg"]},
+        "modes": {k: dict(ms_per_step=v["ms_per_step"], value=v["value"], steps=v["steps"],
+                          kernels_ms_avg={c: d["ms_avg"] for c, d in v["kernels"].items()})
+                  for k, v in results.items()},
+    }
+    if fp64:
+        out["fp64_plain"] = results[fp64]["value"]
+        out["speedup_vs_fp64"] = r["value"] / results[fp64]["value"]
+        ref = finals[fp64]
+        out["rel_err_vs_fp64"] = float(np.abs(finals[head] - ref).max() / np.abs(ref).max())
+    if not args.no_cpu:
+        log("[bench] oracle baseline on the host")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

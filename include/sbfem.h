@@ -43,8 +43,15 @@ typedef enum {
 typedef enum { SBFEM_PROD_FP64 = 0, SBFEM_PROD_FP32 = 1, SBFEM_PROD_FP16 = 2, SBFEM_PROD_BF16 = 3 } sbfem_prod;
 /* Storage of the displacement history u_n, u_{n-1}. */
 typedef enum { SBFEM_STATE_FP64 = 0, SBFEM_STATE_FP32 = 1, SBFEM_STATE_KAHAN32 = 2 } sbfem_state;
-/* Assembly of R_int: floating-point atomics, or colour by colour (bitwise reproducible). */
-typedef enum { SBFEM_ASM_ATOMIC = 0, SBFEM_ASM_COLOUR = 1 } sbfem_asm;
+/*
+ * Assembly of R_int:
+ *  ATOMIC  element forces scattered with floating-point atomics, separate update pass;
+ *  COLOUR  cells processed colour by colour (no two cells of a colour share a node),
+ *          plain read-modify-write, bitwise reproducible, separate update pass;
+ *  TILED   owner tiles: each block owns a run of nodes, sums the rows of every cell
+ *          touching them in on-chip memory and updates them in the same pass.
+ */
+typedef enum { SBFEM_ASM_ATOMIC = 0, SBFEM_ASM_COLOUR = 1, SBFEM_ASM_TILED = 2 } sbfem_asm;
 /* Load-time function P(t) (Sec. 5, eqs. Ricker, Triangle, Lamb). */
 typedef enum { SBFEM_LOAD_RICKER = 0, SBFEM_LOAD_TRIANGLE = 1, SBFEM_LOAD_SINE_BURST = 2 } sbfem_load_kind;
 
@@ -151,6 +158,18 @@ sbfem_status sbfem_write_state(sbfem_mesh* m, const double* u_n, const double* u
 
 /* Device bytes held by a mesh, and the number of cells per pattern-size class (diagnostics). */
 sbfem_status sbfem_mesh_info(const sbfem_mesh* m, int64_t* device_bytes, int64_t* n_dof, int32_t* n_colours);
+
+/*
+ * Kernel timing for diagnostics.  With profiling enabled, every kernel launch
+ * of step_n / step_batch on this mesh is bracketed by HIP events recorded on
+ * the launch stream.  profile_read waits for the recorded work, returns the
+ * summed milliseconds and launch counts per kernel class, and clears them.
+ * Classes: 0 load, 1 element kernel of 8-node cells, 2 element kernel of
+ * larger cells, 3 central-difference update.
+ */
+#define SBFEM_N_KERNEL_CLASSES 4
+sbfem_status sbfem_profile(sbfem_mesh* m, int32_t enable);
+sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches);
 
 /* Last error message of the calling thread ("" if none). */
 const char* sbfem_last_error(void);

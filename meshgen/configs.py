@@ -54,6 +54,14 @@ def _run_params(mesh, fm=2.0, P0=1.0, dt_factor=0.5, n_steps=1000, alpha=0.0):
                      dt_factor=float(dt_factor), n_steps=int(n_steps), alpha=float(alpha))
 
 
+def _id_grid(mesh):
+    shape = tuple(r * (1 << mesh.lmax) + 1 for r in mesh.roots)
+    grid = np.full(int(np.prod(shape)), -1, dtype=np.int32)
+    nl = mesh.node_lat.astype(np.int64)
+    grid[(nl[:, 0] * shape[1] + nl[:, 1]) * shape[2] + nl[:, 2]] = np.arange(mesh.n_nodes, dtype=np.int32)
+    return grid
+
+
 def point_load(mesh, xyz, direction, magnitude=1.0):
     scale = 2.0 ** mesh.lmax / mesh.h0
     lat = np.rint(np.asarray(xyz, dtype=np.float64) * scale).astype(np.int64)
@@ -101,6 +109,7 @@ def patch_load(mesh, face, centre, size, pressure=1.0):
     sel, area = sel[keep], area[keep]
     inward = 1.0 if side == 0 else -1.0
     forces = {}
+    mesh.meta["_id_grid"] = _id_grid(mesh)
     for db in (0, 1):
         for dc in (0, 1):
             p = lat[sel].copy()
@@ -111,6 +120,7 @@ def patch_load(mesh, face, centre, size, pressure=1.0):
             nid = node_id_lookup(mesh, p)
             for n, a in zip(nid, area):
                 forces[int(n)] = forces.get(int(n), 0.0) + 0.25 * pressure * a * inward
+    mesh.meta.pop("_id_grid", None)
     nodes = np.array(sorted(forces), dtype=np.int64)
     mesh.load_dof = 3 * nodes + axis
     mesh.load_val = np.array([forces[int(n)] for n in nodes], dtype=np.float64)
@@ -241,16 +251,21 @@ def ellipsoids(seed, n=3):
     return out
 
 
-def _ellipsoid_radius(x, ells):
-    """min over ellipsoids of the scaled radius sqrt(sum((R^T(x-c)/a)^2)); <=1 inside."""
-    r = np.full(x.shape[0], np.inf)
-    for c, a, R in ells:
-        y = (x - c) @ R
-        r = np.minimum(r, np.sqrt(((y / a) ** 2).sum(1)))
-    return r
+def _ellipsoid_radius(x, ells, chunk=1 << 22):
+    """min over ellipsoids of the scaled radius sqrt(sum((R^T(x-c)/a)^2)); <=1 inside.
+    Evaluated in chunks; returns float32."""
+    out = np.empty(x.shape[0], dtype=np.float32)
+    for lo in range(0, x.shape[0], chunk):
+        xs = x[lo:lo + chunk]
+        r2 = np.full(xs.shape[0], np.inf, dtype=np.float64)
+        for c, a, R in ells:
+            y = (xs - c) @ (R / a[None, :])
+            np.minimum(r2, np.einsum("ij,ij->i", y, y), out=r2)
+        out[lo:lo + chunk] = np.sqrt(r2)
+    return out
 
 
-def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=0.35, keep_node_lat=True, nu=0.25):
+def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=1.05, keep_node_lat=True, nu=0.25):
     """Ellipsoid-inclusion octree (cfg3 recipe): level lfine where the scaled
     ellipsoid radius is below 1+band, level lcoarse elsewhere; E=5, rho=2 inside."""
     ells = ellipsoids(seed)
@@ -278,7 +293,7 @@ def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=0.35, keep_node_lat=True, nu
 
 
 def cfg3(seed=0, n_steps=200, keep_node_lat=False):
-    m = inclusion_mesh(seed=seed, lcoarse=8, lfine=9, band=0.35, keep_node_lat=keep_node_lat)
+    m = inclusion_mesh(seed=seed, lcoarse=8, lfine=9, band=1.05, keep_node_lat=keep_node_lat)
     _run_params(m, fm=4.0, n_steps=n_steps)
     m.meta["name"] = "cfg3 ellipsoid inclusions L8/9"
     return m

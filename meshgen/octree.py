@@ -6,8 +6,9 @@ Refinement is decided top-down by a caller-supplied predicate; the 2:1 rule
 over face, edge and corner neighbours in one fine-to-coarse sweep: if a cell
 at level l+1 is refined, every level-l cell that touches it must be refined.
 
-Nodes are deduplicated on the integer lattice of spacing ``h0 * 2**-lmax``
-and numbered along a Morton curve; cells are ordered along the same curve.
+Nodes are deduplicated on the integer lattice of spacing ``h0 * 2**-lmax``.
+Cells are ordered along the Morton curve and nodes are numbered in the order
+the cells first touch them (the heavy part runs in ``native/octree_gen.cpp``).
 Face-centre nodes follow the face discretisation reading used throughout
 this project: a face gets a centre node unless it has no mid-edge node or
 exactly two on opposite edges (the two cases that tile by rectangles alone).
@@ -18,7 +19,7 @@ from dataclasses import dataclass, field
 import numpy as np
 from scipy import ndimage
 
-from .slots import CORNERS, EDGES, FACES, popcount32
+from .slots import EDGES, FACES
 
 # edges bounding each face (indices into EDGES), and which pairs are parallel
 FACE_EDGES = []
@@ -46,20 +47,6 @@ def face_centre_bits(edge_mask):
         has = (nh >= 1) & ~opposite
         out |= has.astype(np.uint32) << np.uint32(f)
     return out
-
-
-def _part1by2(v):
-    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
-    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
-    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
-    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
-    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
-    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
-    return v
-
-
-def morton3(x, y, z):
-    return _part1by2(x) | (_part1by2(y) << np.uint64(1)) | (_part1by2(z) << np.uint64(2))
 
 
 @dataclass
@@ -141,153 +128,100 @@ def refine_levels(roots, lmin, lmax, refine):
     return refined
 
 
+_NATIVE = None
+
+
+def _native():
+    """Load (building on first use) the native leaf/node/connectivity routine."""
+    global _NATIVE
+    if _NATIVE is not None:
+        return _NATIVE
+    import ctypes
+    import os
+    import subprocess
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "native")
+    src = os.path.join(here, "octree_gen.cpp")
+    lib = os.path.join(here, "libog.so")
+    if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        build_native()
+    L = ctypes.CDLL(lib)
+    P = ctypes.c_void_p
+    L.og_build.argtypes = [P, ctypes.c_int, P, P]
+    L.og_fetch.argtypes = [P, P, P, P, P, P]
+    _NATIVE = L
+    return L
+
+
+def build_native():
+    import os
+    import subprocess
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "native")
+    src = os.path.join(here, "octree_gen.cpp")
+    lib = os.path.join(here, "libog.so")
+    tmp = lib + ".tmp"
+    subprocess.run(["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", src, "-o", tmp], check=True)
+    os.replace(tmp, lib)
+    return lib
+
+
 def build_mesh(roots, h0, lmin, lmax, refine, material=None, mat_E=(1.0,), mat_rho=(1.0,),
                nu=0.25, fixed=None, keep_node_lat=True):
     """Build a balanced octree mesh.
 
     material(xyz_centres (k,3)) -> uint8 material id per cell (default all 0).
     fixed(node_lat (k,3) int, lmax) -> bool (k,3) fixed dofs (default: none).
+    Cells follow the Morton curve; nodes are numbered in first-touch order
+    along it (corners, mid-edge nodes, face centres of each cell in turn).
     """
+    import ctypes
     roots = tuple(int(r) for r in roots)
-    refined = refine_levels(roots, lmin, lmax, refine)
-    lat_shape = tuple(r * (1 << lmax) + 1 for r in roots)
-    node_flag = np.zeros(lat_shape, dtype=bool)
+    refined = [np.ascontiguousarray(r, dtype=np.uint8) for r in refine_levels(roots, lmin, lmax, refine)]
+    L = _native()
+    ptrs = (ctypes.c_void_p * max(1, len(refined)))(*[r.ctypes.data for r in refined])
+    rts = np.array(roots, dtype=np.int64)
+    counts = np.zeros(3, dtype=np.int64)
+    if L.og_build(rts.ctypes.data, int(lmax), ptrs, counts.ctypes.data) != 0:
+        raise RuntimeError("octree generation failed")
+    del refined
+    C, n_nodes, n_conn = (int(v) for v in counts)
+    cell_level = np.empty(C, dtype=np.uint8)
+    cell_lat = np.empty((C, 3), dtype=np.int32)
+    cell_slots = np.empty(C, dtype=np.uint32)
+    conn_ptr = np.empty(C + 1, dtype=np.int64)
+    conn = np.empty(n_conn, dtype=np.int32)
+    node_lat = np.empty((n_nodes, 3), dtype=np.int32)
+    L.og_fetch(cell_level.ctypes.data, cell_lat.ctypes.data, cell_slots.ctypes.data,
+               conn_ptr.ctypes.data, conn.ctypes.data, node_lat.ctypes.data)
 
-    # leaves per level
-    leaves = []
-    for lev in range(lmax + 1):
-        ex = np.ones(roots, dtype=bool) if lev == 0 else _upsample(refined[lev - 1])
-        lf = ex & ~refined[lev] if lev < lmax else ex
-        leaves.append(lf)
-        if not lf.any():
-            continue
-        s = 1 << (lmax - lev)
-        cg = np.zeros(tuple(n + 1 for n in lf.shape), dtype=bool)
-        for di in (0, 1):
-            for dj in (0, 1):
-                for dk in (0, 1):
-                    cg[di:di + lf.shape[0], dj:dj + lf.shape[1], dk:dk + lf.shape[2]] |= lf
-        node_flag[::s, ::s, ::s] |= cg
-
-    # per-level leaf coordinates and edge masks (mid-edge present iff a finer corner sits there)
-    lat_list, lev_list, slot_list = [], [], []
-    for lev in range(lmax + 1):
-        lf = leaves[lev]
-        if not lf.any():
-            continue
-        idx = np.argwhere(lf).astype(np.int64)
-        s = 1 << (lmax - lev)
-        lat = idx * s
-        emask = np.zeros(idx.shape[0], dtype=np.uint32)
-        if lev < lmax:
-            half = s // 2
-            for e in range(12):
-                off = (EDGES[e] + 1) * half
-                p = lat + off
-                emask |= node_flag[p[:, 0], p[:, 1], p[:, 2]].astype(np.uint32) << np.uint32(e)
-        lat_list.append(lat)
-        lev_list.append(np.full(idx.shape[0], lev, dtype=np.uint8))
-        slot_list.append(emask)
-        del idx
-
-    # face centres (after every edge mask is known), then mark those nodes
-    for i, lat in enumerate(lat_list):
-        lev = int(lev_list[i][0])
-        fbits = face_centre_bits(slot_list[i])
-        slot_list[i] = slot_list[i] | (fbits << np.uint32(12))
-        if lev < lmax:
-            half = (1 << (lmax - lev)) // 2
-            for f in range(6):
-                sel = ((fbits >> np.uint32(f)) & np.uint32(1)).astype(bool)
-                if sel.any():
-                    p = lat[sel] + (FACES[f] + 1) * half
-                    node_flag[p[:, 0], p[:, 1], p[:, 2]] = True
-
-    cell_lat = np.concatenate(lat_list).astype(np.int32)
-    cell_level = np.concatenate(lev_list)
-    cell_slots = np.concatenate(slot_list)
-    del lat_list, lev_list, slot_list
-
-    # Morton order of cells (by min corner)
-    key = morton3(cell_lat[:, 0], cell_lat[:, 1], cell_lat[:, 2])
-    order = np.argsort(key, kind="stable")
-    del key
-    cell_lat = cell_lat[order]
-    cell_level = cell_level[order]
-    cell_slots = cell_slots[order]
-    del order
-
-    # Morton numbering of nodes
-    nidx = np.flatnonzero(node_flag)
-    del node_flag
-    nz = np.unravel_index(nidx, lat_shape)
-    nkey = morton3(nz[0], nz[1], nz[2])
-    norder = np.argsort(nkey, kind="stable")
-    del nkey
-    nidx = nidx[norder]
-    n_nodes = int(nidx.shape[0])
-    id_grid = np.full(int(np.prod(lat_shape)), -1, dtype=np.int32)
-    id_grid[nidx] = np.arange(n_nodes, dtype=np.int32)
-    node_lat = None
-    if keep_node_lat:
-        node_lat = np.stack(np.unravel_index(nidx, lat_shape), axis=1).astype(np.int32)
-    del nz, norder
-
-    # connectivity in natural slot order
-    nper = 8 + popcount32(cell_slots).astype(np.int64)
-    conn_ptr = np.zeros(cell_level.shape[0] + 1, dtype=np.int64)
-    np.cumsum(nper, out=conn_ptr[1:])
-    conn = np.full(int(conn_ptr[-1]), -1, dtype=np.int32)
-    half = (np.int64(1) << (lmax - cell_level.astype(np.int64))) // 2  # 0 for lmax cells
     full = np.int64(1) << (lmax - cell_level.astype(np.int64))
-    sy, sz = lat_shape[1] * lat_shape[2], lat_shape[2]
-
-    def flat(p):
-        return p[:, 0] * sy + p[:, 1] * sz + p[:, 2]
-
-    for c in range(8):
-        off = (CORNERS[c] + 1) // 2  # 0 or 1
-        p = cell_lat.astype(np.int64) + off[None, :] * full[:, None]
-        conn[conn_ptr[:-1] + c] = id_grid[flat(p)]
-    for b in range(18):
-        sel = np.flatnonzero((cell_slots >> np.uint32(b)) & np.uint32(1))
-        if sel.shape[0] == 0:
-            continue
-        pos = EDGES[b] if b < 12 else FACES[b - 12]
-        rank = 8 + popcount32(cell_slots[sel] & np.uint32((1 << b) - 1)).astype(np.int64)
-        p = cell_lat[sel].astype(np.int64) + (pos[None, :] + 1) * half[sel, None]
-        conn[conn_ptr[sel] + rank] = id_grid[flat(p)]
-    del id_grid
-    if (conn < 0).any():
-        raise RuntimeError("mesh generator produced a dangling slot")
-
-    centres = (cell_lat.astype(np.float64) + 0.5 * full[:, None]) * (h0 * 2.0 ** -lmax)
     if material is None:
-        cell_mat = np.zeros(cell_level.shape[0], dtype=np.uint8)
+        cell_mat = np.zeros(C, dtype=np.uint8)
     else:
+        centres = (cell_lat.astype(np.float64) + 0.5 * full[:, None]) * (h0 * 2.0 ** -lmax)
         cell_mat = np.asarray(material(centres), dtype=np.uint8)
-    del centres
+        del centres
     fx = np.zeros(3 * n_nodes, dtype=np.uint8)
     if fixed is not None:
-        if node_lat is None:
-            raise ValueError("fixed() needs node lattice coordinates")
         fx = np.asarray(fixed(node_lat, lmax), dtype=np.uint8).reshape(-1)
-    return Mesh(roots=roots, h0=float(h0), lmax=int(lmax), n_nodes=n_nodes,
-                cell_level=cell_level, cell_lat=cell_lat, cell_slots=cell_slots,
-                conn_ptr=conn_ptr, conn=conn, node_lat=node_lat, cell_mat=cell_mat,
-                mat_E=np.asarray(mat_E, dtype=np.float64),
-                mat_rho=np.asarray(mat_rho, dtype=np.float64), nu=float(nu), fixed=fx)
+    m = Mesh(roots=roots, h0=float(h0), lmax=int(lmax), n_nodes=n_nodes,
+             cell_level=cell_level, cell_lat=cell_lat, cell_slots=cell_slots,
+             conn_ptr=conn_ptr, conn=conn, node_lat=node_lat, cell_mat=cell_mat,
+             mat_E=np.asarray(mat_E, dtype=np.float64),
+             mat_rho=np.asarray(mat_rho, dtype=np.float64), nu=float(nu), fixed=fx)
+    return m
 
 
 def node_id_lookup(mesh, lat):
     """Node ids at lattice points (k,3); -1 where no node exists."""
     lat = np.asarray(lat, dtype=np.int64).reshape(-1, 3)
-    lat_shape = tuple(r * (1 << mesh.lmax) + 1 for r in mesh.roots)
-    nl = mesh.node_lat.astype(np.int64)
-    keys = (nl[:, 0] * lat_shape[1] + nl[:, 1]) * lat_shape[2] + nl[:, 2]
-    q = (lat[:, 0] * lat_shape[1] + lat[:, 1]) * lat_shape[2] + lat[:, 2]
-    order = np.argsort(keys)
-    pos = np.searchsorted(keys[order], q)
-    pos = np.clip(pos, 0, keys.shape[0] - 1)
-    hit = keys[order][pos] == q
-    return np.where(hit, order[pos], -1)
+    shape = tuple(r * (1 << mesh.lmax) + 1 for r in mesh.roots)
+    grid = mesh.meta.get("_id_grid") if isinstance(mesh.meta, dict) else None
+    if grid is None:
+        grid = np.full(int(np.prod(shape)), -1, dtype=np.int32)
+        nl = mesh.node_lat.astype(np.int64)
+        grid[(nl[:, 0] * shape[1] + nl[:, 1]) * shape[2] + nl[:, 2]] = np.arange(mesh.n_nodes, dtype=np.int32)
+    ok = (lat >= 0).all(1) & (lat[:, 0] < shape[0]) & (lat[:, 1] < shape[1]) & (lat[:, 2] < shape[2])
+    out = np.full(len(lat), -1, dtype=np.int64)
+    q = (lat[ok, 0] * shape[1] + lat[ok, 1]) * shape[2] + lat[ok, 2]
+    out[ok] = grid[q]
+    return out

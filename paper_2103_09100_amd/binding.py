@@ -21,13 +21,14 @@ _lib = C.CDLL(LIB_PATH)
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY = 0, -1, -2, -3, -4, -5
 PROD = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 STATE = {"fp64": 0, "fp32": 1, "kahan32": 2}
-ASM = {"atomic": 0, "colour": 1}
+ASM = {"atomic": 0, "colour": 1, "tiled": 2}
 LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
 
 EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint",
            "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n",
            "sbfem_step_batch", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
-           "sbfem_last_error"]
+           "sbfem_profile", "sbfem_profile_read", "sbfem_last_error"]
+KERNEL_CLASSES = ("load", "element_8node", "element_larger", "update")
 
 
 class MeshDesc(C.Structure):
@@ -60,6 +61,8 @@ _lib.sbfem_step_batch.argtypes = [_P, C.c_int32, _P, _P]
 _lib.sbfem_read_state.argtypes = [_P, C.c_int32, _P, C.POINTER(C.c_int64), _P]
 _lib.sbfem_write_state.argtypes = [_P, _P, _P, C.c_int64, _P]
 _lib.sbfem_mesh_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+_lib.sbfem_profile.argtypes = [_P, C.c_int32]
+_lib.sbfem_profile_read.argtypes = [_P, _P, _P]
 _lib.sbfem_last_error.argtypes = []
 _lib.sbfem_last_error.restype = C.c_char_p
 for _name in EXPORTS:
@@ -206,6 +209,15 @@ class Mesh:
         b, n, c = C.c_int64(), C.c_int64(), C.c_int32()
         _check(_lib.sbfem_mesh_info(self.handle, C.byref(b), C.byref(n), C.byref(c)))
         return dict(device_bytes=b.value, n_dof=n.value, n_colours=c.value)
+
+    def profile(self, enable=True):
+        _check(_lib.sbfem_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self):
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
+        _check(_lib.sbfem_profile_read(self.handle, ms.ctypes.data, n.ctypes.data))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def close(self):
         if self.handle:

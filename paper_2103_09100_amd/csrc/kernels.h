@@ -7,6 +7,64 @@
 namespace sbfem {
 
 constexpr int kTile = 256;  // cells per block (one cell per thread)
+constexpr int kWave = 64;
+
+// Owner tile: a block updates the nodes [own0, own0 + n_own) (internal ids).
+// Its local nodes are the owned ones (local i < n_own is node own0 + i) followed
+// by the other nodes its cells touch (local i >= n_own is nodelist[node0 + i - n_own]);
+// u of all of them is staged in LDS.
+struct OwnerTile {
+  int64_t node0;
+  int64_t own0;
+  int64_t item0;
+  int32_t n_own;
+  int32_t n_local;
+  int32_t n_items;
+  int32_t load0;
+  int32_t n_load;
+  int32_t pad;
+};
+
+// Up to one wave of cells of one pattern; rows (master slots) in mask are accumulated.
+struct CellItem {
+  int64_t lidx0;   // local node indices, slot-major: lidx[lidx0 + k*count + lane]
+  int64_t cell0;   // per-cell orientation/level/material
+  int64_t koff;    // master matrix offset
+  int32_t nn;
+  int32_t count;
+  uint32_t mask;
+  int32_t pad;
+};
+
+struct LoadEntry {
+  int32_t ldof;    // 3 * local owned node + axis
+  int32_t pad;
+  double val;
+};
+
+struct TiledArgs {
+  const OwnerTile* tiles;
+  int64_t n_tiles;
+  const CellItem* items;
+  const uint16_t* lidx;
+  const uint8_t* orient;
+  const uint8_t* level;
+  const uint8_t* material;
+  const int32_t* nodelist;
+  const LoadEntry* loads;
+  const double* matE;
+  double h0;
+  const double* K64;
+  const float* K32;
+  const double* u;      // u_n
+  double* um1;          // u_{n-1} in, u_{n+1} out (owned nodes)
+  const double* minv;
+  double* f;            // force-only mode: R_int of owned dofs written here
+  double P;             // P(t_n)
+  double dt2;
+  double c;             // alpha dt / 2
+  int32_t lds_doubles;  // dynamic LDS size in doubles
+};
 
 // A block's work: up to kTile consecutive cells of one pattern segment.
 struct Tile {
@@ -46,7 +104,29 @@ struct ElementArgs {
   const float* K32;
 };
 
-hipError_t launch_ebe(const ElementArgs& a, const TileRange& r, bool fp32, bool atomic, hipStream_t s);
+// Optional per-class event hook: called before (begin=true) and after each launch.
+struct LaunchHook {
+  void (*fn)(void* ctx, int cls, bool begin, hipStream_t s) = nullptr;
+  void* ctx = nullptr;
+  void operator()(int cls, bool begin, hipStream_t s) const {
+    if (fn) fn(ctx, cls, begin, s);
+  }
+};
+
+hipError_t launch_ebe(const ElementArgs& a, const TileRange& r, bool fp32, bool atomic, hipStream_t s,
+                      const LaunchHook& hook = LaunchHook());
+// One time step over owner tiles (tiles [0, n_pure8) hold 8-node cells only, the next
+// n_mixed any pattern).  force_only: write R_int of the owned dofs to a.f instead of updating.
+hipError_t launch_tiled(const TiledArgs& a, int64_t n_pure8, int64_t n_mixed, bool fp32, bool force_only,
+                        hipStream_t s, const LaunchHook& hook = LaunchHook());
+// per-unit launchers
+void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, bool atomic, hipStream_t s);
+void ebe_mixed_fp64_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
+void ebe_mixed_fp32_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
+void tiled_pure8_launch(const TiledArgs& a, int64_t first, int64_t count, bool fp32, bool force_only, hipStream_t s);
+void tiled_mixed_fp64_launch(const TiledArgs& a, int64_t first, int64_t count, bool force_only, hipStream_t s);
+void tiled_mixed_fp32_launch(const TiledArgs& a, int64_t first, int64_t count, bool force_only, hipStream_t s);
+
 hipError_t launch_load(double* f, const int64_t* idx, const double* val, int64_t nnz, const LoadParams& L,
                        double t, hipStream_t s);
 hipError_t launch_update(const double* un, double* unm1, double* f, const double* minv, int64_t ndof,

@@ -20,6 +20,7 @@
 
 #include "../../include/sbfem.h"
 #include "kernels.h"
+#include "tiling.h"
 
 namespace {
 
@@ -119,12 +120,29 @@ struct sbfem_mesh {
   hipEvent_t flag_ev = nullptr;
   bool flag_pending = false;
   std::vector<sbfem::TileRange> groups;  // one per colour
+  // kernel timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (class, index of the begin event)
   int64_t step = 0;
   int64_t bytes = 0;
   int n_colours = 1;
+  // internal node numbering (first touch along the cell order)
+  std::vector<int32_t> int2ext;
+  // owner tiles
+  sbfem::OwnerTile* otiles = nullptr;
+  sbfem::CellItem* items = nullptr;
+  uint16_t* lidx = nullptr;
+  int32_t* nodelist = nullptr;
+  sbfem::LoadEntry* tloads = nullptr;
+  int64_t n_pure8 = 0, n_mixed = 0;
+  int32_t lds_doubles = 0;
 };
 
 namespace {
+
+constexpr int32_t kOwnerTileNodes = 512;  // nodes owned by one block in the tiled assembly
 
 sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
   if (!p || !d) return fail(SBFEM_EINVAL, "null patterns or descriptor");
@@ -144,7 +162,7 @@ sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
   if (d->prod != SBFEM_PROD_FP64 && d->prod != SBFEM_PROD_FP32)
     return fail(SBFEM_EINVAL, "product precision %d not available", d->prod);
   if (d->state != SBFEM_STATE_FP64) return fail(SBFEM_EINVAL, "state storage %d not available", d->state);
-  if (d->assembly != SBFEM_ASM_ATOMIC && d->assembly != SBFEM_ASM_COLOUR)
+  if (d->assembly != SBFEM_ASM_ATOMIC && d->assembly != SBFEM_ASM_COLOUR && d->assembly != SBFEM_ASM_TILED)
     return fail(SBFEM_EINVAL, "unknown assembly mode");
   for (int64_t c = 0; c < d->n_cells; ++c) {
     if (d->pattern[c] >= p->n) return fail(SBFEM_EINVAL, "cell %lld: pattern %d out of range", (long long)c, d->pattern[c]);
@@ -260,6 +278,7 @@ sbfem_status sbfem_critical_dt(const sbfem_patterns* p, const sbfem_mesh_desc* d
 void sbfem_destroy_mesh(sbfem_mesh* m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
+  for (auto e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->flag_ev) (void)hipEventDestroy(m->flag_ev);
   if (m->flag_h) (void)hipHostFree(m->flag_h);
   dfree(m->u);
@@ -275,6 +294,11 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->load_idx);
   dfree(m->load_val);
   dfree(m->flag_d);
+  dfree(m->otiles);
+  dfree(m->items);
+  dfree(m->lidx);
+  dfree(m->nodelist);
+  dfree(m->tloads);
   delete m;
 }
 
@@ -294,11 +318,62 @@ static sbfem::ElementArgs element_args(const sbfem_mesh* m) {
   return a;
 }
 
+static void profile_hook(void* ctx, int cls, bool begin, hipStream_t s) {
+  auto* m = (sbfem_mesh*)ctx;
+  if (m->ev_used == m->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    m->ev_pool.push_back(e);
+  }
+  if (begin) m->ev_marks.push_back({cls, m->ev_used});
+  (void)hipEventRecord(m->ev_pool[m->ev_used++], s);
+}
+
+static sbfem::LaunchHook hook_of(sbfem_mesh* m) {
+  sbfem::LaunchHook h;
+  if (m->profiling) {
+    h.fn = profile_hook;
+    h.ctx = m;
+  }
+  return h;
+}
+
 // f += R_int(u) over all colours (f must hold what it should be added to)
+static sbfem::TiledArgs tiled_args(sbfem_mesh* m) {
+  sbfem::TiledArgs a{};
+  a.tiles = m->otiles;
+  a.n_tiles = m->n_pure8 + m->n_mixed;
+  a.items = m->items;
+  a.lidx = m->lidx;
+  a.orient = m->orient;
+  a.level = m->level;
+  a.material = m->material;
+  a.nodelist = m->nodelist;
+  a.loads = m->tloads;
+  a.matE = m->matE;
+  a.h0 = m->h0;
+  a.K64 = m->P->dK64;
+  a.K32 = m->P->dK32;
+  a.u = m->u;
+  a.um1 = m->um1;
+  a.minv = m->minv;
+  a.f = m->f;
+  a.dt2 = m->dt * m->dt;
+  a.c = 0.5 * m->alpha * m->dt;
+  a.lds_doubles = m->lds_doubles;
+  return a;
+}
+
 static sbfem_status internal_force(sbfem_mesh* m, hipStream_t s) {
+  if (m->assembly == SBFEM_ASM_TILED) {
+    sbfem::TiledArgs a = tiled_args(m);
+    HIP_TRY(sbfem::launch_tiled(a, m->n_pure8, m->n_mixed, m->prod == SBFEM_PROD_FP32, true, s, hook_of(m)));
+    return SBFEM_OK;
+  }
   sbfem::ElementArgs a = element_args(m);
   const bool atomic = m->assembly == SBFEM_ASM_ATOMIC;
-  for (const auto& g : m->groups) HIP_TRY(sbfem::launch_ebe(a, g, m->prod == SBFEM_PROD_FP32, atomic, s));
+  const sbfem::LaunchHook h = hook_of(m);
+  for (const auto& g : m->groups) HIP_TRY(sbfem::launch_ebe(a, g, m->prod == SBFEM_PROD_FP32, atomic, s, h));
   return SBFEM_OK;
 }
 
@@ -319,37 +394,25 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     if (d->conn[i] < 0 || d->conn[i] >= N)
       return fail(SBFEM_EINVAL, "node id %d at conn[%lld] out of range", d->conn[i], (long long)i);
 
-  // colours: greedy in input order, per-node mask of the colours already touching it
-  std::vector<uint8_t> colour(C, 0);
-  int n_colours = 1;
-  if (d->assembly == SBFEM_ASM_COLOUR) {
-    std::vector<uint64_t> used(N, 0);
-    for (int64_t c = 0; c < C; ++c) {
-      uint64_t forb = 0;
-      for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) forb |= used[d->conn[i]];
-      if (forb == ~0ull) return fail(SBFEM_EINVAL, "cell %lld needs more than 64 colours", (long long)c);
-      int col = 0;
-      while ((forb >> col) & 1) ++col;
-      colour[c] = (uint8_t)col;
-      n_colours = std::max(n_colours, col + 1);
-      for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) used[d->conn[i]] |= 1ull << col;
-    }
-  }
-
-  // order: colour, 8-node class first, pattern; stable in input order (counting sort)
-  const int64_t n_keys = (int64_t)n_colours * 2 * p->n;
-  auto key = [&](int64_t c) -> int64_t {
-    const int pid = d->pattern[c];
-    const int mixed = p->ndof[pid] == 24 ? 0 : 1;
-    return ((int64_t)colour[c] * 2 + mixed) * p->n + pid;
-  };
-  std::vector<int64_t> order(C);
+  // internal numbering: first touch along the cell order (nodes used by no cell go last)
+  std::vector<int32_t> ext2int(N, -1), int2ext(N);
   {
-    std::vector<int64_t> start(n_keys + 1, 0);
-    for (int64_t c = 0; c < C; ++c) start[key(c) + 1]++;
-    for (int64_t k = 0; k < n_keys; ++k) start[k + 1] += start[k];
-    for (int64_t c = 0; c < C; ++c) order[start[key(c)]++] = c;
+    int32_t next = 0;
+    for (int64_t i = 0; i < total; ++i) {
+      const int32_t g = d->conn[i];
+      if (ext2int[g] < 0) {
+        ext2int[g] = next;
+        int2ext[next++] = g;
+      }
+    }
+    for (int64_t g = 0; g < N; ++g)
+      if (ext2int[g] < 0) {
+        ext2int[g] = next;
+        int2ext[next++] = (int32_t)g;
+      }
   }
+  std::vector<int32_t> iconn(total);
+  for (int64_t i = 0; i < total; ++i) iconn[i] = ext2int[d->conn[i]];
 
   auto* m = new sbfem_mesh();
   m->P = p;
@@ -367,53 +430,8 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   m->L.cycles = d->load_cycles;
   m->L.t1 = d->load_t1;
   m->L.P0 = d->load_P0;
-  m->n_colours = n_colours;
 
-  // segments, tiles and slot-major node ids
-  std::vector<int32_t> sconn(total);
-  std::vector<uint8_t> sorient(C), slevel(C), smat(C);
-  std::vector<sbfem::Tile> tiles;
-  m->groups.assign(n_colours, sbfem::TileRange{0, 0, 0});
-  int64_t cpos = 0, i0 = 0;
-  for (int col = 0; col < n_colours; ++col) m->groups[col].first = -1;
-  while (i0 < C) {
-    int64_t i1 = i0;
-    const int64_t k0 = key(order[i0]);
-    while (i1 < C && key(order[i1]) == k0) ++i1;
-    const int pid = d->pattern[order[i0]];
-    const int nn = p->ndof[pid] / 3;
-    const int col = colour[order[i0]];
-    const int64_t cnt = i1 - i0;
-    for (int64_t j = 0; j < cnt; ++j) {
-      const int64_t c = order[i0 + j];
-      for (int k = 0; k < nn; ++k) sconn[cpos + (int64_t)k * cnt + j] = d->conn[cptr[c] + k];
-      sorient[i0 + j] = d->orient[c];
-      slevel[i0 + j] = d->level[c];
-      smat[i0 + j] = d->material[c];
-    }
-    auto& g = m->groups[col];
-    if (g.first < 0) g.first = (int64_t)tiles.size();
-    for (int64_t j = 0; j < cnt; j += sbfem::kTile) {
-      sbfem::Tile t;
-      t.cell0 = i0 + j;
-      t.conn0 = cpos + j;
-      t.stride = cnt;
-      t.koff = p->koff[pid];
-      t.count = (int32_t)std::min<int64_t>(sbfem::kTile, cnt - j);
-      t.nn = nn;
-      tiles.push_back(t);
-      if (nn == 8)
-        g.n_fixed8++;
-      else
-        g.n_mixed++;
-    }
-    cpos += cnt * nn;
-    i0 = i1;
-  }
-  for (auto& g : m->groups)
-    if (g.first < 0) g.first = 0;
-
-  // lumped diagonal mass (input order; summation order fixed)
+  // lumped diagonal mass in internal numbering (summation order fixed: cell order)
   std::vector<double> mdiag(ndof, 0.0);
   for (int64_t c = 0; c < C; ++c) {
     const int pid = d->pattern[c];
@@ -424,30 +442,32 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     decode(d->orient[c], pi, sg);
     const double* mp = p->m.data() + p->moff[pid];
     for (int64_t k = 0; k < cptr[c + 1] - cptr[c]; ++k)
-      for (int a = 0; a < 3; ++a) mdiag[3 * (int64_t)d->conn[cptr[c] + k] + pi[a]] += sc * mp[3 * k + a];
+      for (int a = 0; a < 3; ++a) mdiag[3 * (int64_t)iconn[cptr[c] + k] + pi[a]] += sc * mp[3 * k + a];
   }
   std::vector<double> minv(ndof);
   for (int64_t i = 0; i < ndof; ++i) {
-    const bool fixed = d->fixed_dof && d->fixed_dof[i];
+    const int64_t e = 3 * (int64_t)int2ext[i / 3] + i % 3;
+    const bool fixed = d->fixed_dof && d->fixed_dof[e];
     if (fixed) {
       minv[i] = 0.0;
     } else {
       if (!(mdiag[i] > 0)) {
         sbfem_destroy_mesh(m);
-        return fail(SBFEM_EINVAL, "free dof %lld has no mass (node not used by any cell?)", (long long)i);
+        return fail(SBFEM_EINVAL, "free dof %lld has no mass (node not used by any cell?)", (long long)e);
       }
       minv[i] = 1.0 / mdiag[i];
     }
   }
 
-  // load vector with merged duplicates
+  // load vector (internal dofs) with merged duplicates
   std::map<int64_t, double> bmap;
   for (int64_t i = 0; i < d->load_nnz; ++i) {
     if (d->load_dof[i] < 0 || d->load_dof[i] >= ndof) {
       sbfem_destroy_mesh(m);
       return fail(SBFEM_EINVAL, "load dof %lld out of range", (long long)d->load_dof[i]);
     }
-    bmap[d->load_dof[i]] += d->load_val[i];
+    const int64_t e = d->load_dof[i];
+    bmap[3 * (int64_t)ext2int[e / 3] + e % 3] += d->load_val[i];
   }
   std::vector<int64_t> bidx;
   std::vector<double> bval;
@@ -460,38 +480,169 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   std::vector<double> matE(256, 0.0);
   for (int i = 0; i < d->n_materials; ++i) matE[i] = d->E[i];
 
-  m->bytes = footprint_bytes(p, d, total);
   hipError_t e = hipSuccess;
-#define ALLOC(ptr, n)                                      \
-  if (e == hipSuccess) e = dalloc(&m->ptr, (size_t)(n));
+  auto H2D = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  int64_t bytes = ndof * 8 * 4 + 256 * 8 + 64;
+#define ALLOC(ptr, n)                                            \
+  if (e == hipSuccess) {                                         \
+    e = dalloc(&m->ptr, (size_t)(n));                            \
+    bytes += (int64_t)(n) * (int64_t)sizeof(*m->ptr);            \
+  }
   ALLOC(u, ndof)
   ALLOC(um1, ndof)
   ALLOC(f, ndof)
   ALLOC(minv, ndof)
   ALLOC(matE, 256)
-  ALLOC(conn, total)
-  ALLOC(orient, C)
-  ALLOC(level, C)
-  ALLOC(material, C)
-  ALLOC(tiles, tiles.size())
-  ALLOC(load_idx, m->nnz)
-  ALLOC(load_val, m->nnz)
   ALLOC(flag_d, 1)
+
+  if (d->assembly == SBFEM_ASM_TILED) {
+    sbfem::TilingInput ti;
+    ti.n_nodes = N;
+    ti.n_cells = C;
+    ti.cptr = cptr.data();
+    ti.conn = iconn.data();
+    ti.pattern = d->pattern;
+    ti.orient = d->orient;
+    ti.level = d->level;
+    ti.material = d->material;
+    ti.pattern_ndof = p->ndof.data();
+    ti.pattern_koff = p->koff.data();
+    ti.load_dof = bidx;
+    ti.load_val = bval;
+    sbfem::TilingOutput to;
+    // halve the tile until one block's LDS (u of its local nodes + f of its owned ones) fits 64 KiB
+    bool ok = false;
+    for (int32_t tn = kOwnerTileNodes; tn >= 32; tn /= 2) {
+      if (sbfem::build_owner_tiles(ti, tn, to) && 24 * (to.max_local + to.tile_nodes) <= 65536) {
+        ok = true;
+        break;
+      }
+    }
+    if (!ok) {
+      sbfem_destroy_mesh(m);
+      return fail(SBFEM_EINVAL, "no owner-tile size fits the on-chip memory of a block");
+    }
+    m->n_pure8 = to.n_pure8;
+    m->n_mixed = to.n_mixed;
+    m->lds_doubles = (int32_t)(3 * (to.max_local + to.tile_nodes));
+    ALLOC(otiles, to.tiles.size())
+    ALLOC(items, to.items.size())
+    ALLOC(lidx, to.lidx.size())
+    ALLOC(nodelist, to.nodelist.size())
+    ALLOC(tloads, to.loads.size())
+    ALLOC(orient, to.orient.size())
+    ALLOC(level, to.level.size())
+    ALLOC(material, to.material.size())
+    H2D(m->otiles, to.tiles.data(), to.tiles.size() * sizeof(sbfem::OwnerTile));
+    H2D(m->items, to.items.data(), to.items.size() * sizeof(sbfem::CellItem));
+    H2D(m->lidx, to.lidx.data(), to.lidx.size() * 2);
+    H2D(m->nodelist, to.nodelist.data(), to.nodelist.size() * 4);
+    H2D(m->tloads, to.loads.data(), to.loads.size() * sizeof(sbfem::LoadEntry));
+    H2D(m->orient, to.orient.data(), to.orient.size());
+    H2D(m->level, to.level.data(), to.level.size());
+    H2D(m->material, to.material.data(), to.material.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers of `to` die below
+  } else {
+    // colours: greedy in input order, per-node mask of the colours already touching it
+    std::vector<uint8_t> colour(C, 0);
+    int n_colours = 1;
+    if (d->assembly == SBFEM_ASM_COLOUR) {
+      std::vector<uint64_t> used(N, 0);
+      for (int64_t c = 0; c < C; ++c) {
+        uint64_t forb = 0;
+        for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) forb |= used[iconn[i]];
+        if (forb == ~0ull) {
+          sbfem_destroy_mesh(m);
+          return fail(SBFEM_EINVAL, "cell %lld needs more than 64 colours", (long long)c);
+        }
+        int col = 0;
+        while ((forb >> col) & 1) ++col;
+        colour[c] = (uint8_t)col;
+        n_colours = std::max(n_colours, col + 1);
+        for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) used[iconn[i]] |= 1ull << col;
+      }
+    }
+    m->n_colours = n_colours;
+    // order: colour, 8-node class first, pattern; stable in input order (counting sort)
+    const int64_t n_keys = (int64_t)n_colours * 2 * p->n;
+    auto key = [&](int64_t c) -> int64_t {
+      const int pid = d->pattern[c];
+      const int mixed = p->ndof[pid] == 24 ? 0 : 1;
+      return ((int64_t)colour[c] * 2 + mixed) * p->n + pid;
+    };
+    std::vector<int64_t> order(C);
+    {
+      std::vector<int64_t> start(n_keys + 1, 0);
+      for (int64_t c = 0; c < C; ++c) start[key(c) + 1]++;
+      for (int64_t k = 0; k < n_keys; ++k) start[k + 1] += start[k];
+      for (int64_t c = 0; c < C; ++c) order[start[key(c)]++] = c;
+    }
+    // segments, tiles and slot-major node ids
+    std::vector<int32_t> sconn(total);
+    std::vector<uint8_t> sorient(C), slevel(C), smat(C);
+    std::vector<sbfem::Tile> tiles;
+    m->groups.assign(n_colours, sbfem::TileRange{-1, 0, 0});
+    int64_t cpos = 0, i0 = 0;
+    while (i0 < C) {
+      int64_t i1 = i0;
+      const int64_t k0 = key(order[i0]);
+      while (i1 < C && key(order[i1]) == k0) ++i1;
+      const int pid = d->pattern[order[i0]];
+      const int nn = p->ndof[pid] / 3;
+      const int col = colour[order[i0]];
+      const int64_t cnt = i1 - i0;
+      for (int64_t j = 0; j < cnt; ++j) {
+        const int64_t c = order[i0 + j];
+        for (int k = 0; k < nn; ++k) sconn[cpos + (int64_t)k * cnt + j] = iconn[cptr[c] + k];
+        sorient[i0 + j] = d->orient[c];
+        slevel[i0 + j] = d->level[c];
+        smat[i0 + j] = d->material[c];
+      }
+      auto& g = m->groups[col];
+      if (g.first < 0) g.first = (int64_t)tiles.size();
+      for (int64_t j = 0; j < cnt; j += sbfem::kTile) {
+        sbfem::Tile t;
+        t.cell0 = i0 + j;
+        t.conn0 = cpos + j;
+        t.stride = cnt;
+        t.koff = p->koff[pid];
+        t.count = (int32_t)std::min<int64_t>(sbfem::kTile, cnt - j);
+        t.nn = nn;
+        tiles.push_back(t);
+        if (nn == 8)
+          g.n_fixed8++;
+        else
+          g.n_mixed++;
+      }
+      cpos += cnt * nn;
+      i0 = i1;
+    }
+    for (auto& g : m->groups)
+      if (g.first < 0) g.first = 0;
+    ALLOC(conn, total)
+    ALLOC(orient, C)
+    ALLOC(level, C)
+    ALLOC(material, C)
+    ALLOC(tiles, tiles.size())
+    ALLOC(load_idx, m->nnz)
+    ALLOC(load_val, m->nnz)
+    H2D(m->conn, sconn.data(), total * 4);
+    H2D(m->orient, sorient.data(), C);
+    H2D(m->level, slevel.data(), C);
+    H2D(m->material, smat.data(), C);
+    H2D(m->tiles, tiles.data(), tiles.size() * sizeof(sbfem::Tile));
+    H2D(m->load_idx, bidx.data(), m->nnz * 8);
+    H2D(m->load_val, bval.data(), m->nnz * 8);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
 #undef ALLOC
+  m->bytes = bytes;
   if (e == hipSuccess) e = hipHostMalloc((void**)&m->flag_h, sizeof(int32_t), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&m->flag_ev, hipEventDisableTiming);
-  auto H2D = [&](void* dst, const void* src, size_t bytes) {
-    if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
-  };
   H2D(m->minv, minv.data(), ndof * 8);
   H2D(m->matE, matE.data(), 256 * 8);
-  H2D(m->conn, sconn.data(), total * 4);
-  H2D(m->orient, sorient.data(), C);
-  H2D(m->level, slevel.data(), C);
-  H2D(m->material, smat.data(), C);
-  H2D(m->tiles, tiles.data(), tiles.size() * sizeof(sbfem::Tile));
-  H2D(m->load_idx, bidx.data(), m->nnz * 8);
-  H2D(m->load_val, bval.data(), m->nnz * 8);
   if (e == hipSuccess) e = hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s);
   if (e == hipSuccess) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
   if (e != hipSuccess) {
@@ -503,10 +654,12 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
 
   // start-up point (eq. D0): u_-1 = u0 - dt v0 + dt^2/2 a0,  a0 = M^-1 (P(0) b - K u0) - alpha v0
   std::vector<double> u0(ndof, 0.0), v0(ndof, 0.0), ku0(ndof, 0.0);
-  if (d->u0) std::copy(d->u0, d->u0 + ndof, u0.begin());
-  if (d->v0) std::copy(d->v0, d->v0 + ndof, v0.begin());
-  for (int64_t i = 0; i < ndof; ++i)
+  for (int64_t i = 0; i < ndof; ++i) {
+    const int64_t ex = 3 * (int64_t)int2ext[i / 3] + i % 3;
+    if (d->u0) u0[i] = d->u0[ex];
+    if (d->v0) v0[i] = d->v0[ex];
     if (minv[i] == 0.0) u0[i] = v0[i] = 0.0;
+  }
   H2D(m->u, u0.data(), ndof * 8);
   if (e == hipSuccess && d->u0) {
     sbfem_status fs = internal_force(m, s);
@@ -532,6 +685,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     sbfem_destroy_mesh(m);
     return fail(SBFEM_EDEVICE, "create_mesh initial state: %s", hipGetErrorString(e));
   }
+  m->int2ext.swap(int2ext);
   *out = m;
   return SBFEM_OK;
 }
@@ -548,10 +702,23 @@ static sbfem_status check_flag(sbfem_mesh* m) {
 
 static sbfem_status enqueue_step(sbfem_mesh* m, hipStream_t s) {
   const double t = (double)m->step * m->dt;
+  const sbfem::LaunchHook h = hook_of(m);
+  if (m->assembly == SBFEM_ASM_TILED) {
+    sbfem::TiledArgs a = tiled_args(m);
+    a.P = load_time_host(m->L, t);
+    HIP_TRY(sbfem::launch_tiled(a, m->n_pure8, m->n_mixed, m->prod == SBFEM_PROD_FP32, false, s, h));
+    std::swap(m->u, m->um1);
+    m->step++;
+    return SBFEM_OK;
+  }
+  h(0, true, s);
   HIP_TRY(sbfem::launch_load(m->f, m->load_idx, m->load_val, m->nnz, m->L, t, s));
+  h(0, false, s);
   sbfem_status st = internal_force(m, s);
   if (st != SBFEM_OK) return st;
+  h(3, true, s);
   HIP_TRY(sbfem::launch_update(m->u, m->um1, m->f, m->minv, m->ndof, m->dt * m->dt, 0.5 * m->alpha * m->dt, s));
+  h(3, false, s);
   std::swap(m->u, m->um1);
   m->step++;
   return SBFEM_OK;
@@ -609,15 +776,17 @@ sbfem_status sbfem_read_state(sbfem_mesh* m, int32_t which, double* host_out, in
   if (which < 0 || which > 2) return fail(SBFEM_EINVAL, "which must be 0, 1 or 2");
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<double> tmp(m->ndof);
   if (which == 2) {
     sbfem_status st = internal_force(m, s);
     if (st != SBFEM_OK) return st;
-    HIP_TRY(hipMemcpyAsync(host_out, m->f, m->ndof * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(tmp.data(), m->f, m->ndof * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(sbfem::launch_fill(m->f, m->ndof, 0.0, s));
   } else {
-    HIP_TRY(hipMemcpyAsync(host_out, which == 0 ? m->u : m->um1, m->ndof * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(tmp.data(), which == 0 ? m->u : m->um1, m->ndof * 8, hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < m->ndof; ++i) host_out[3 * (int64_t)m->int2ext[i / 3] + i % 3] = tmp[i];
   if (step) *step = m->step;
   return check_flag(m);
 }
@@ -628,12 +797,43 @@ sbfem_status sbfem_write_state(sbfem_mesh* m, const double* u_n, const double* u
   if (step < 0) return fail(SBFEM_EINVAL, "negative step");
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t s = (hipStream_t)hip_stream;
-  HIP_TRY(hipMemcpyAsync(m->u, u_n, m->ndof * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(m->um1, u_nm1, m->ndof * 8, hipMemcpyHostToDevice, s));
+  std::vector<double> a(m->ndof), b(m->ndof);
+  for (int64_t i = 0; i < m->ndof; ++i) {
+    const int64_t e = 3 * (int64_t)m->int2ext[i / 3] + i % 3;
+    a[i] = u_n[e];
+    b[i] = u_nm1[e];
+  }
+  HIP_TRY(hipMemcpyAsync(m->u, a.data(), m->ndof * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(m->um1, b.data(), m->ndof * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s));
   HIP_TRY(hipStreamSynchronize(s));
   m->step = step;
   m->flag_pending = false;
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_profile(sbfem_mesh* m, int32_t enable) {
+  if (!m) return fail(SBFEM_EINVAL, "null mesh");
+  m->profiling = enable != 0;
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches) {
+  if (!m || !ms || !launches) return fail(SBFEM_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(m->device));
+  for (int c = 0; c < SBFEM_N_KERNEL_CLASSES; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (auto& mk : m->ev_marks) {
+    HIP_TRY(hipEventSynchronize(m->ev_pool[mk.second + 1]));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, m->ev_pool[mk.second], m->ev_pool[mk.second + 1]));
+    ms[mk.first] += t;
+    launches[mk.first] += 1;
+  }
+  m->ev_marks.clear();
+  m->ev_used = 0;
   return SBFEM_OK;
 }
 

@@ -1,0 +1,201 @@
+// Host set-up of the owner-tile layout (see kernels.h, OwnerTile).
+//
+// Nodes carry internal ids in first-touch order along the cell sequence, so a
+// run of consecutive ids is a spatially compact set.  Tile t owns the ids
+// [t*T, (t+1)*T).  Its work is every cell that touches an owned node; for each
+// such cell only the rows of owned nodes are accumulated.  Cells are grouped
+// into wave-sized items of one pattern and one row mask so that the master
+// matrix and the row selection are uniform within a wave.
+#include <algorithm>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tiling.h"
+
+namespace sbfem {
+
+namespace {
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+  unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (n < 64) nt = 1;
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < nt; ++w)
+    th.emplace_back([&, w] {
+      for (int64_t i = w; i < n; i += nt) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+struct TileOut {
+  std::vector<int32_t> local;      // global ids of local nodes (owned first)
+  std::vector<CellItem> items;     // offsets relative to this tile
+  std::vector<uint16_t> lidx;
+  std::vector<uint8_t> orient, level, material;
+  std::vector<LoadEntry> loads;
+  bool pure8 = true;
+};
+
+}  // namespace
+
+bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& out) {
+  const int64_t N = in.n_nodes, C = in.n_cells;
+  // node -> cells (internal ids), cells in increasing order
+  std::vector<int64_t> nptr(N + 1, 0);
+  for (int64_t i = 0; i < in.cptr[C]; ++i) nptr[in.conn[i] + 1]++;
+  for (int64_t n = 0; n < N; ++n) nptr[n + 1] += nptr[n];
+  std::vector<int32_t> ncell(nptr[N]);
+  {
+    std::vector<int64_t> pos(nptr.begin(), nptr.end() - 1);
+    for (int64_t c = 0; c < C; ++c)
+      for (int64_t i = in.cptr[c]; i < in.cptr[c + 1]; ++i) ncell[pos[in.conn[i]]++] = (int32_t)c;
+  }
+  // load entries by node
+  std::unordered_map<int64_t, double> bmap;
+  for (size_t i = 0; i < in.load_dof.size(); ++i) bmap[in.load_dof[i]] += in.load_val[i];
+
+  const int64_t n_tiles = (N + tile_nodes - 1) / tile_nodes;
+  std::vector<TileOut> res(n_tiles);
+  parallel_for(n_tiles, [&](int64_t t) {
+    TileOut& r = res[t];
+    const int64_t own0 = t * tile_nodes, own1 = std::min<int64_t>(N, own0 + tile_nodes);
+    std::vector<int32_t> cells;
+    for (int64_t n = own0; n < own1; ++n)
+      for (int64_t i = nptr[n]; i < nptr[n + 1]; ++i) cells.push_back(ncell[i]);
+    std::sort(cells.begin(), cells.end());
+    cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+    // local numbering: owned nodes first (in id order), then others on first sight
+    for (int64_t n = own0; n < own1; ++n) r.local.push_back((int32_t)n);
+    std::unordered_map<int32_t, int32_t> other;
+    struct CellRec { int32_t c; uint32_t mask; int32_t pattern; };
+    std::vector<CellRec> recs;
+    std::vector<uint16_t> li_flat;
+    std::vector<int64_t> li_off(cells.size() + 1, 0);
+    for (size_t j = 0; j < cells.size(); ++j) {
+      const int32_t c = cells[j];
+      uint32_t mask = 0;
+      for (int64_t i = in.cptr[c]; i < in.cptr[c + 1]; ++i) {
+        const int32_t g = in.conn[i];
+        int32_t l;
+        if (g >= own0 && g < own1) {
+          l = (int32_t)(g - own0);
+          mask |= 1u << (i - in.cptr[c]);
+        } else {
+          auto it = other.find(g);
+          if (it == other.end()) {
+            l = (int32_t)r.local.size();
+            other.emplace(g, l);
+            r.local.push_back(g);
+          } else {
+            l = it->second;
+          }
+        }
+        li_flat.push_back((uint16_t)l);
+      }
+      li_off[j + 1] = (int64_t)li_flat.size();
+      if (in.pattern_ndof[in.pattern[c]] != 24) r.pure8 = false;
+      recs.push_back({(int32_t)j, mask, (int32_t)in.pattern[c]});
+    }
+    // group by (pattern, row mask); small groups of one pattern share an item with the union mask
+    std::sort(recs.begin(), recs.end(), [](const CellRec& a, const CellRec& b) {
+      return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
+    });
+    const size_t kMerge = 16;
+    size_t i0 = 0;
+    std::vector<std::vector<CellRec>> groups;
+    std::vector<CellRec> small;
+    int32_t small_pat = -1;
+    auto flush_small = [&] {
+      if (!small.empty()) groups.push_back(small);
+      small.clear();
+    };
+    while (i0 < recs.size()) {
+      size_t i1 = i0;
+      while (i1 < recs.size() && recs[i1].pattern == recs[i0].pattern && recs[i1].mask == recs[i0].mask) ++i1;
+      std::vector<CellRec> g(recs.begin() + i0, recs.begin() + i1);
+      if (g.size() < kMerge) {
+        if (small_pat != g[0].pattern) flush_small();
+        small_pat = g[0].pattern;
+        small.insert(small.end(), g.begin(), g.end());
+      } else {
+        groups.push_back(g);
+      }
+      i0 = i1;
+    }
+    flush_small();
+    for (auto& g : groups) {
+      for (size_t a = 0; a < g.size(); a += kWave) {
+        const size_t cnt = std::min<size_t>(kWave, g.size() - a);
+        CellItem it{};
+        const int32_t pid = g[a].pattern;
+        const int nn = in.pattern_ndof[pid] / 3;
+        it.lidx0 = (int64_t)r.lidx.size();
+        it.cell0 = (int64_t)r.orient.size();
+        it.koff = in.pattern_koff[pid];
+        it.nn = nn;
+        it.count = (int32_t)cnt;
+        it.mask = 0;
+        for (size_t b = 0; b < cnt; ++b) it.mask |= g[a + b].mask;
+        for (int k = 0; k < nn; ++k)
+          for (size_t b = 0; b < cnt; ++b) r.lidx.push_back(li_flat[li_off[g[a + b].c] + k]);
+        for (size_t b = 0; b < cnt; ++b) {
+          const int32_t c = cells[g[a + b].c];
+          r.orient.push_back(in.orient[c]);
+          r.level.push_back(in.level[c]);
+          r.material.push_back(in.material[c]);
+        }
+        r.items.push_back(it);
+      }
+    }
+    for (int64_t n = own0; n < own1; ++n)
+      for (int a = 0; a < 3; ++a) {
+        auto it = bmap.find(3 * n + a);
+        if (it != bmap.end()) r.loads.push_back({(int32_t)(3 * (n - own0) + a), 0, it->second});
+      }
+  });
+
+  // concatenate: pure 8-node tiles first, then the others
+  out = TilingOutput();
+  out.tile_nodes = tile_nodes;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int64_t t = 0; t < n_tiles; ++t) {
+      TileOut& r = res[t];
+      if (r.pure8 != (pass == 0)) continue;
+      OwnerTile ot{};
+      ot.own0 = t * tile_nodes;
+      ot.n_own = (int32_t)std::min<int64_t>(tile_nodes, N - ot.own0);
+      ot.node0 = (int64_t)out.nodelist.size();
+      ot.n_local = (int32_t)r.local.size();
+      ot.item0 = (int64_t)out.items.size();
+      ot.n_items = (int32_t)r.items.size();
+      ot.load0 = (int32_t)out.loads.size();
+      ot.n_load = (int32_t)r.loads.size();
+      out.max_local = std::max<int64_t>(out.max_local, ot.n_local);
+      if (ot.n_local > 65535) return false;
+      const int64_t lbase = (int64_t)out.lidx.size(), cbase = (int64_t)out.orient.size();
+      for (auto it : r.items) {
+        it.lidx0 += lbase;
+        it.cell0 += cbase;
+        out.items.push_back(it);
+      }
+      // owned nodes are implicit (own0 + i); only the others are listed
+      out.nodelist.insert(out.nodelist.end(), r.local.begin() + ot.n_own, r.local.end());
+      out.lidx.insert(out.lidx.end(), r.lidx.begin(), r.lidx.end());
+      out.orient.insert(out.orient.end(), r.orient.begin(), r.orient.end());
+      out.level.insert(out.level.end(), r.level.begin(), r.level.end());
+      out.material.insert(out.material.end(), r.material.begin(), r.material.end());
+      out.loads.insert(out.loads.end(), r.loads.begin(), r.loads.end());
+      out.tiles.push_back(ot);
+      if (pass == 0)
+        out.n_pure8++;
+      else
+        out.n_mixed++;
+      r = TileOut();
+    }
+  }
+  return true;
+}
+
+}  // namespace sbfem

@@ -83,20 +83,31 @@ def canonicalise(mesh, seed=None):
             pick = (rng.random(len(e)) * cnt).astype(np.int64)
             code[lo:lo + len(e)] = np.argmax(np.cumsum(valid, axis=1) > pick[:, None], axis=1)
     key = slots * 64 + code
-    ukeys, inv = np.unique(key, return_inverse=True)
-    order = np.argsort(inv, kind="stable")
-    bounds = np.concatenate([[0], np.cumsum(np.bincount(inv, minlength=len(ukeys)))])
     conn = np.asarray(mesh.conn)
     ptr = np.asarray(mesh.conn_ptr)
-    out = np.empty_like(conn)
-    for j, k in enumerate(ukeys):
+    out = conn.copy()
+    # distinct (layout, orientation) pairs; those whose node map is the identity need no work
+    present_keys = np.flatnonzero(np.bincount(key, minlength=1))
+    moving = np.zeros(int(present_keys.max()) + 1, dtype=bool)
+    perms = {}
+    for k in present_keys:
         sm, c = int(k // 64), int(k % 64)
         p = tab.pattern_of[sm & 0xFFF]
         # the cell's face-centre nodes must land on its master's
         if int(pt.transform_slot_masks([sm], c)[0]) != int(tab.master_mask[p]):
             raise ValueError("cell layout is not a transformed master cell")
         perm = tab.conn_permutation(sm, c)
-        cells = order[bounds[j]:bounds[j + 1]]
-        base = ptr[cells][:, None]
-        out[base + np.arange(len(perm))[None, :]] = conn[base + perm[None, :]]
+        if not np.array_equal(perm, np.arange(len(perm))):
+            moving[k] = True
+            perms[int(k)] = perm
+    sel = np.flatnonzero(moving[key])
+    if sel.size:
+        ks = key[sel]
+        order = np.argsort(ks, kind="stable")
+        sel, ks = sel[order], ks[order]
+        cuts = np.flatnonzero(np.diff(ks)) + 1
+        for cells, k in zip(np.split(sel, cuts), ks[np.concatenate([[0], cuts])]):
+            perm = perms[int(k)]
+            base = ptr[cells][:, None]
+            out[base + np.arange(len(perm))[None, :]] = conn[base + perm[None, :]]
     return pid.astype(np.uint16), code.astype(np.uint8), out
