@@ -126,6 +126,8 @@ def main():
                     help="assembly variants timed beside the headline over --compare-steps steps")
     ap.add_argument("--compare-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -147,6 +149,14 @@ def main():
     log(f"[bench] algorithmic bytes/step {ab['step'] / 1e9:.3f} GB ({ab['step'] / mesh.n_dof:.1f} B/dof)")
 
     stream = torch.cuda.Stream()
+    if args.copy_probe:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 3 x (read 1 GiB, write 1 GiB) elementwise kernel")
+        del x, y
     results = {}
     finals = {}
     plan = [(m, args.steps, args.warmup) for m in args.modes.split(",") if m]
@@ -156,7 +166,7 @@ def main():
         t1 = time.time()
         sim = Simulation(mesh, prod=prod, assembly=assembly, stream=stream.cuda_stream)
         log(f"[bench] {mode}: created in {time.time() - t1:.0f} s, dt={sim.dt:.4e}, "
-            f"{sim.gpu.info()['n_colours']} colours, {sim.footprint / 1e9:.1f} GB")
+            f"{sim.gpu.info()['n_colours']} colours, {sim.footprint / 1e9:.1f} GB, layout {sim.gpu.layout()}")
         ms = time_mode(sim, torch, stream, n_steps, n_warm)
         prof = profile_mode(sim, torch, stream, n_steps)
         finals[mode] = sim.u()

@@ -171,6 +171,15 @@ sbfem_status sbfem_mesh_info(const sbfem_mesh* m, int64_t* device_bytes, int64_t
 sbfem_status sbfem_profile(sbfem_mesh* m, int32_t enable);
 sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches);
 
+/*
+ * Layout statistics (diagnostics): vals[0..n_vals) receives, in order,
+ *  0 owner tiles with 8-node cells only, 1 other owner tiles, 2 cell items,
+ *  3 local node entries over all tiles, 4 cell entries over all tiles (cells
+ *  touching several tiles count once per tile), 5 nodes owned per tile.
+ * Entries not available for the mesh's assembly are 0.
+ */
+sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals);
+
 /* Last error message of the calling thread ("" if none). */
 const char* sbfem_last_error(void);
 

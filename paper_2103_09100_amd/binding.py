@@ -27,7 +27,7 @@ LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
 EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint",
            "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n",
            "sbfem_step_batch", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
-           "sbfem_profile", "sbfem_profile_read", "sbfem_last_error"]
+           "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_last_error"]
 KERNEL_CLASSES = ("load", "element_8node", "element_larger", "update")
 
 
@@ -63,6 +63,7 @@ _lib.sbfem_write_state.argtypes = [_P, _P, _P, C.c_int64, _P]
 _lib.sbfem_mesh_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
 _lib.sbfem_profile.argtypes = [_P, C.c_int32]
 _lib.sbfem_profile_read.argtypes = [_P, _P, _P]
+_lib.sbfem_mesh_layout.argtypes = [_P, _P, C.c_int32]
 _lib.sbfem_last_error.argtypes = []
 _lib.sbfem_last_error.restype = C.c_char_p
 for _name in EXPORTS:
@@ -209,6 +210,13 @@ class Mesh:
         b, n, c = C.c_int64(), C.c_int64(), C.c_int32()
         _check(_lib.sbfem_mesh_info(self.handle, C.byref(b), C.byref(n), C.byref(c)))
         return dict(device_bytes=b.value, n_dof=n.value, n_colours=c.value)
+
+    LAYOUT = ("tiles_8node", "tiles_other", "items", "local_nodes", "cell_entries", "tile_nodes")
+
+    def layout(self):
+        v = np.zeros(len(self.LAYOUT), dtype=np.int64)
+        _check(_lib.sbfem_mesh_layout(self.handle, v.ctypes.data, len(v)))
+        return dict(zip(self.LAYOUT, v.tolist()))
 
     def profile(self, enable=True):
         _check(_lib.sbfem_profile(self.handle, int(bool(enable))))

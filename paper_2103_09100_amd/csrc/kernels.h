@@ -56,6 +56,9 @@ struct TiledArgs {
   double h0;
   const double* K64;
   const float* K32;
+  const double* W64;    // 8-node master matrix as 8 blocks of 3x3 in the corner Walsh basis (or null)
+  const float* W32;
+  int64_t walsh_koff;   // master-matrix offset of the 8-node pattern (-1: none)
   const double* u;      // u_n
   double* um1;          // u_{n-1} in, u_{n+1} out (owned nodes)
   const double* minv;
@@ -64,6 +67,8 @@ struct TiledArgs {
   double dt2;
   double c;             // alpha dt / 2
   int32_t lds_doubles;  // dynamic LDS size in doubles
+  int32_t block_threads;        // 8-node tiles: 64..512, multiple of 64
+  int32_t block_threads_mixed;  // other tiles
 };
 
 // A block's work: up to kTile consecutive cells of one pattern segment.

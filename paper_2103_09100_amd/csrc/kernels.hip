@@ -119,10 +119,12 @@ hipError_t launch_tiled(const TiledArgs& a, int64_t n_pure8, int64_t n_mixed, bo
   }
   if (n_mixed > 0) {
     hook(2, true, s);
+    TiledArgs b = a;
+    b.block_threads = a.block_threads_mixed;
     if (fp32)
-      tiled_mixed_fp32_launch(a, n_pure8, n_mixed, force_only, s);
+      tiled_mixed_fp32_launch(b, n_pure8, n_mixed, force_only, s);
     else
-      tiled_mixed_fp64_launch(a, n_pure8, n_mixed, force_only, s);
+      tiled_mixed_fp64_launch(b, n_pure8, n_mixed, force_only, s);
     hook(2, false, s);
   }
   return hipGetLastError();
@@ -146,12 +148,19 @@ void tiled_pure8_launch(const TiledArgs& a, int64_t first, int64_t count, bool f
                         hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
   const size_t lds = (size_t)a.lds_doubles * 8;
-#define SBFEM_L(F, O) \
-  hipLaunchKernelGGL((tiled_step<true, F, O>), dim3((unsigned)blocks), dim3(256), lds, s, a, first, count)
+  const bool walsh = a.walsh_koff >= 0;
+#define SBFEM_L(F, W)                                                                                    \
+  do {                                                                                                   \
+    if (lds > 65536)                                                                                     \
+      (void)hipFuncSetAttribute((const void*)tiled_step<true, F, W>,                                     \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
+    hipLaunchKernelGGL((tiled_step<true, F, W>), dim3((unsigned)blocks), dim3(a.block_threads), lds, s, a, \
+                       first, count, (int)force_only);                                                   \
+  } while (0)
   if (fp32) {
-    if (force_only) SBFEM_L(true, true); else SBFEM_L(true, false);
+    if (walsh) SBFEM_L(true, true); else SBFEM_L(true, false);
   } else {
-    if (force_only) SBFEM_L(false, true); else SBFEM_L(false, false);
+    if (walsh) SBFEM_L(false, true); else SBFEM_L(false, false);
   }
 #undef SBFEM_L
 }

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -93,6 +94,10 @@ struct sbfem_patterns {
   std::vector<double> K, m, omega;
   double* dK64 = nullptr;
   float* dK32 = nullptr;
+  // 8-node pattern in the corner Walsh basis (8 blocks of 3x3), if its matrix has that structure
+  int64_t walsh_koff = -1;
+  double* dW64 = nullptr;
+  float* dW32 = nullptr;
 };
 
 struct sbfem_mesh {
@@ -138,6 +143,10 @@ struct sbfem_mesh {
   sbfem::LoadEntry* tloads = nullptr;
   int64_t n_pure8 = 0, n_mixed = 0;
   int32_t lds_doubles = 0;
+  int32_t block_threads = 512;        // 8-node owner tiles
+  int32_t block_threads_mixed = 256;  // owner tiles with larger cells
+  bool walsh = true;
+  int64_t layout[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -222,16 +231,55 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
       return fail(SBFEM_EINVAL, "pattern %d: non-positive frequency", i);
     }
   std::vector<float> K32(p->K.begin(), p->K.end());
+  // Walsh blocks of the 8-node pattern: Khat[(a',s'),(a,s)] = 1/64 sum_{k,k'} chi_s'(k) K[3k+a'][3k'+a] chi_s(k'),
+  // corner k = i + 2j + 4l at (2i-1, 2j-1, 2l-1), chi_s(k) = prod_b p_b^(s_b); used only if every
+  // entry outside the blocks s' = t^(1<<a'), s = t^(1<<a) vanishes to roundoff.
+  std::vector<double> W(72, 0.0);
+  for (int pid = 0; pid < n_patterns; ++pid) {
+    if (p->ndof[pid] != 24) continue;
+    const double* Kp = p->K.data() + p->koff[pid];
+    auto chi = [](int k, int s) {
+      double v = 1.0;
+      for (int b = 0; b < 3; ++b)
+        if ((s >> b) & 1) v *= ((k >> b) & 1) ? 1.0 : -1.0;
+      return v;
+    };
+    double kmax = 0.0, off = 0.0;
+    for (int i = 0; i < 576; ++i) kmax = std::max(kmax, std::fabs(Kp[i]));
+    for (int a2 = 0; a2 < 3; ++a2)
+      for (int s2 = 0; s2 < 8; ++s2)
+        for (int a = 0; a < 3; ++a)
+          for (int s1 = 0; s1 < 8; ++s1) {
+            double v = 0.0;
+            for (int k = 0; k < 8; ++k)
+              for (int k2 = 0; k2 < 8; ++k2) v += chi(k, s2) * Kp[(3 * k + a2) * 24 + 3 * k2 + a] * chi(k2, s1);
+            v /= 64.0;
+            const int t = s1 ^ (1 << a);
+            if ((s2 ^ (1 << a2)) == t)
+              W[t * 9 + a2 * 3 + a] = v;
+            else
+              off = std::max(off, std::fabs(v));
+          }
+    if (off <= 1e-12 * kmax / 8.0) p->walsh_koff = p->koff[pid];
+    break;
+  }
+  std::vector<float> W32(W.begin(), W.end());
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = dalloc(&p->dK64, ko);
   if (e == hipSuccess) e = dalloc(&p->dK32, ko);
   if (e == hipSuccess) e = hipMemcpyAsync(p->dK64, p->K.data(), ko * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(p->dK32, K32.data(), ko * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = dalloc(&p->dW64, 72);
+  if (e == hipSuccess) e = dalloc(&p->dW32, 72);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->dW64, W.data(), 72 * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->dW32, W32.data(), 72 * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     dfree(p->dK64);
     dfree(p->dK32);
+    dfree(p->dW64);
+    dfree(p->dW32);
     delete p;
     return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "pattern upload: %s", hipGetErrorString(e));
   }
@@ -244,6 +292,8 @@ void sbfem_destroy_patterns(sbfem_patterns* p) {
   (void)hipSetDevice(p->device);
   dfree(p->dK64);
   dfree(p->dK32);
+  dfree(p->dW64);
+  dfree(p->dW32);
   delete p;
 }
 
@@ -354,6 +404,9 @@ static sbfem::TiledArgs tiled_args(sbfem_mesh* m) {
   a.h0 = m->h0;
   a.K64 = m->P->dK64;
   a.K32 = m->P->dK32;
+  a.W64 = m->P->dW64;
+  a.W32 = m->P->dW32;
+  a.walsh_koff = m->walsh ? m->P->walsh_koff : -1;
   a.u = m->u;
   a.um1 = m->um1;
   a.minv = m->minv;
@@ -361,6 +414,8 @@ static sbfem::TiledArgs tiled_args(sbfem_mesh* m) {
   a.dt2 = m->dt * m->dt;
   a.c = 0.5 * m->alpha * m->dt;
   a.lds_doubles = m->lds_doubles;
+  a.block_threads = m->block_threads;
+  a.block_threads_mixed = m->block_threads_mixed;
   return a;
 }
 
@@ -512,10 +567,25 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     ti.load_dof = bidx;
     ti.load_val = bval;
     sbfem::TilingOutput to;
-    // halve the tile until one block's LDS (u of its local nodes + f of its owned ones) fits 64 KiB
+    // tile size: env SBFEM_TILE_NODES or the default; halved until one block's LDS
+    // (u of its local nodes + f of its owned ones) fits the per-block limit
+    int lds_max = 65536;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+    if (lds_max < 16384) lds_max = 65536;
+    int32_t tn0 = kOwnerTileNodes;
+    if (const char* ev = std::getenv("SBFEM_TILE_NODES")) tn0 = std::max(32, std::atoi(ev));
+    auto threads_env = [](const char* name, int32_t& v) {
+      if (const char* ev = std::getenv(name)) {
+        const int bt = std::atoi(ev);
+        if (bt >= 64 && bt <= 512 && bt % 64 == 0) v = bt;
+      }
+    };
+    threads_env("SBFEM_BLOCK_THREADS", m->block_threads);
+    threads_env("SBFEM_BLOCK_THREADS_MIXED", m->block_threads_mixed);
+    if (const char* ev = std::getenv("SBFEM_DENSE8")) m->walsh = std::atoi(ev) == 0;
     bool ok = false;
-    for (int32_t tn = kOwnerTileNodes; tn >= 32; tn /= 2) {
-      if (sbfem::build_owner_tiles(ti, tn, to) && 24 * (to.max_local + to.tile_nodes) <= 65536) {
+    for (int32_t tn = tn0; tn >= 32; tn /= 2) {
+      if (sbfem::build_owner_tiles(ti, tn, to) && 24 * (to.max_local + to.tile_nodes) <= lds_max) {
         ok = true;
         break;
       }
@@ -526,6 +596,12 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     }
     m->n_pure8 = to.n_pure8;
     m->n_mixed = to.n_mixed;
+    m->layout[0] = to.n_pure8;
+    m->layout[1] = to.n_mixed;
+    m->layout[2] = (int64_t)to.items.size();
+    m->layout[3] = (int64_t)to.nodelist.size() + N;
+    m->layout[4] = (int64_t)to.orient.size();
+    m->layout[5] = to.tile_nodes;
     m->lds_doubles = (int32_t)(3 * (to.max_local + to.tile_nodes));
     ALLOC(otiles, to.tiles.size())
     ALLOC(items, to.items.size())
@@ -834,6 +910,12 @@ sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches) {
   }
   m->ev_marks.clear();
   m->ev_used = 0;
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals) {
+  if (!m || (n_vals > 0 && !vals)) return fail(SBFEM_EINVAL, "null argument");
+  for (int i = 0; i < n_vals; ++i) vals[i] = i < 6 ? m->layout[i] : 0;
   return SBFEM_OK;
 }
 

@@ -15,7 +15,60 @@
 
 namespace sbfem {
 
-template <int NN, bool FP32>
+
+// The regular 8-node cell is symmetric under the three mirror planes, so in the
+// basis of Walsh functions over its corners (per displacement component) its
+// master matrix splits into 8 blocks of 3x3: mode (a, s) of component a and
+// corner character s couples only to modes of the same parity type s ^ (1 << a).
+// f = K u becomes: forward butterflies (24 adds per component), 72 products,
+// inverse butterflies.  Corner k = i + 2j + 4l sits at (2i-1, 2j-1, 2l-1);
+// W holds the blocks with the 1/64 normalisation folded in.
+template <typename T>
+__device__ __forceinline__ void walsh8_apply(const T* __restrict__ W, const T (&ue)[24], T (&fe)[24]) {
+  T x[3][8];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[a][k] = ue[3 * k + a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (!((k >> b) & 1)) {
+          const T lo = x[a][k], hi = x[a][k | (1 << b)];
+          x[a][k] = lo + hi;
+          x[a][k | (1 << b)] = hi - lo;
+        }
+  T y[3][8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int a2 = 0; a2 < 3; ++a2) {
+      T acc = W[t * 9 + a2 * 3 + 0] * x[0][t ^ 1];
+      acc = fma(W[t * 9 + a2 * 3 + 1], x[1][t ^ 2], acc);
+      acc = fma(W[t * 9 + a2 * 3 + 2], x[2][t ^ 4], acc);
+      y[a2][t ^ (1 << a2)] = acc;
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (!((k >> b) & 1)) {
+          const T A = y[a][k], B = y[a][k | (1 << b)];
+          y[a][k] = A - B;
+          y[a][k | (1 << b)] = A + B;
+        }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) fe[3 * k + a] = y[a][k];
+}
+
+template <int NN, bool FP32, int WALSH = 0>  // WALSH: 0 runtime choice, 1 always (8-node only)
 __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it, int lane, int n_own,
                                           const double* __restrict__ ul, double* __restrict__ fl) {
   constexpr int ND = 3 * NN;
@@ -38,6 +91,22 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
       ue[3 * k + 1] = s1 * pick3(p1, x, y, z);
       ue[3 * k + 2] = s2 * pick3(p2, x, y, z);
     }
+    if constexpr (NN == 8) {
+      if (WALSH == 1 || it.koff == a.walsh_koff) {  // uniform in the wave
+        double fe[24];
+        walsh8_apply<double>(a.W64, ue, fe);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (!((mask >> k) & 1u)) continue;
+          if (li[k] >= n_own) continue;
+          atomicAdd(fl + 3 * li[k] + p0, s0 * se * fe[3 * k + 0]);
+          atomicAdd(fl + 3 * li[k] + p1, s1 * se * fe[3 * k + 1]);
+          atomicAdd(fl + 3 * li[k] + p2, s2 * se * fe[3 * k + 2]);
+        }
+        return;
+      }
+    }
+    if constexpr (WALSH == 1) return;
     const double* Kp = a.K64 + it.koff;
 #pragma unroll
     for (int k = 0; k < NN; ++k) {
@@ -66,6 +135,22 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
       ue[3 * k + 1] = (float)(s1 * pick3(p1, x, y, z));
       ue[3 * k + 2] = (float)(s2 * pick3(p2, x, y, z));
     }
+    if constexpr (NN == 8) {
+      if (WALSH == 1 || it.koff == a.walsh_koff) {
+        float fe[24];
+        walsh8_apply<float>(a.W32, ue, fe);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (!((mask >> k) & 1u)) continue;
+          if (li[k] >= n_own) continue;
+          atomicAdd(fl + 3 * li[k] + p0, s0 * se * (double)fe[3 * k + 0]);
+          atomicAdd(fl + 3 * li[k] + p1, s1 * se * (double)fe[3 * k + 1]);
+          atomicAdd(fl + 3 * li[k] + p2, s2 * se * (double)fe[3 * k + 2]);
+        }
+        return;
+      }
+    }
+    if constexpr (WALSH == 1) return;
     const float* Kp = a.K32 + it.koff;
 #pragma unroll
     for (int k = 0; k < NN; ++k) {
@@ -85,8 +170,9 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
   }
 }
 
-template <bool PURE8, bool FP32, bool FORCE_ONLY>
-__global__ void __launch_bounds__(256) tiled_step(TiledArgs a, int64_t first, int64_t count) {
+// PURE8: tiles of 8-node cells only; WALSH (with PURE8): use the block form of the 8-node matrix.
+template <bool PURE8, bool FP32, bool WALSH = false>
+__global__ void __launch_bounds__(512) tiled_step(TiledArgs a, int64_t first, int64_t count, int force_only) {
   extern __shared__ double lds[];
   // XCD-contiguous block -> tile map
   const int64_t per = (count + 7) / 8;
@@ -98,25 +184,27 @@ __global__ void __launch_bounds__(256) tiled_step(TiledArgs a, int64_t first, in
   double* ul = lds;
   double* fl = lds + 3 * (int64_t)n_local;
   const int tid = threadIdx.x;
-  for (int i = tid; i < 3 * n_local; i += 256) {
+  const int nt = blockDim.x;
+  for (int i = tid; i < 3 * n_local; i += nt) {
     const int l = i / 3, c = i - 3 * l;
     const int64_t g = l < n_own ? tile.own0 + l : (int64_t)a.nodelist[tile.node0 + l - n_own];
     ul[i] = a.u[3 * g + c];
   }
-  for (int i = tid; i < 3 * n_own; i += 256) fl[i] = 0.0;
+  for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0.0;
   __syncthreads();
-  if (!FORCE_ONLY)
-    for (int i = tid; i < tile.n_load; i += 256) {
+  if (!force_only)
+    for (int i = tid; i < tile.n_load; i += nt) {
       const LoadEntry e = a.loads[tile.load0 + i];
       atomicAdd(fl + e.ldof, -a.P * e.val);
     }
   // the wave index is uniform in a wave: say so, so item fields (and K_p) come through scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  for (int w = wave; w < tile.n_items; w += 4) {
+  const int n_waves = nt >> 6;
+  for (int w = wave; w < tile.n_items; w += n_waves) {
     const CellItem it = a.items[tile.item0 + w];
     if (lane >= it.count) continue;
     if constexpr (PURE8) {
-      tile_cell<8, FP32>(a, it, lane, n_own, ul, fl);
+      tile_cell<8, FP32, WALSH ? 1 : 0>(a, it, lane, n_own, ul, fl);
     } else {
 #define SBFEM_TCASE(N) \
   case N:              \
@@ -135,11 +223,11 @@ __global__ void __launch_bounds__(256) tiled_step(TiledArgs a, int64_t first, in
   }
   __syncthreads();
   const int64_t d0 = 3 * tile.own0;
-  if (FORCE_ONLY) {
-    for (int i = tid; i < 3 * n_own; i += 256) a.f[d0 + i] = fl[i];
+  if (force_only) {
+    for (int i = tid; i < 3 * n_own; i += nt) a.f[d0 + i] = fl[i];
   } else {
     const double inv = 1.0 / (1.0 + a.c);
-    for (int i = tid; i < 3 * n_own; i += 256) {
+    for (int i = tid; i < 3 * n_own; i += nt) {
       const int64_t d = d0 + i;
       a.um1[d] = (a.dt2 * a.minv[d] * (-fl[i]) + 2.0 * ul[i] - (1.0 - a.c) * a.um1[d]) * inv;
     }
