@@ -66,7 +66,7 @@ struct TiledArgs {
   double P;             // P(t_n)
   double dt2;
   double c;             // alpha dt / 2
-  int32_t lds_doubles;  // dynamic LDS size in doubles
+  int32_t lds_bytes;    // dynamic LDS: 3 FP64 forces per owned node + 3 u values per local node
   int32_t block_threads;        // 8-node tiles: 64..512, multiple of 64
   int32_t block_threads_mixed;  // other tiles
 };

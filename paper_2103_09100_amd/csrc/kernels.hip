@@ -147,7 +147,7 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 void tiled_pure8_launch(const TiledArgs& a, int64_t first, int64_t count, bool fp32, bool force_only,
                         hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
-  const size_t lds = (size_t)a.lds_doubles * 8;
+  const size_t lds = (size_t)a.lds_bytes;
   const bool walsh = a.walsh_koff >= 0;
 #define SBFEM_L(F, W)                                                                                    \
   do {                                                                                                   \

@@ -5,7 +5,7 @@ namespace sbfem {
 
 void tiled_mixed_fp64_launch(const TiledArgs& a, int64_t first, int64_t count, bool force_only, hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
-  const size_t lds = (size_t)a.lds_doubles * 8;
+  const size_t lds = (size_t)a.lds_bytes;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)tiled_step<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);

@@ -142,7 +142,7 @@ struct sbfem_mesh {
   int32_t* nodelist = nullptr;
   sbfem::LoadEntry* tloads = nullptr;
   int64_t n_pure8 = 0, n_mixed = 0;
-  int32_t lds_doubles = 0;
+  int32_t lds_bytes = 0;
   int32_t block_threads = 512;        // 8-node owner tiles
   int32_t block_threads_mixed = 256;  // owner tiles with larger cells
   bool walsh = true;
@@ -413,7 +413,7 @@ static sbfem::TiledArgs tiled_args(sbfem_mesh* m) {
   a.f = m->f;
   a.dt2 = m->dt * m->dt;
   a.c = 0.5 * m->alpha * m->dt;
-  a.lds_doubles = m->lds_doubles;
+  a.lds_bytes = m->lds_bytes;
   a.block_threads = m->block_threads;
   a.block_threads_mixed = m->block_threads_mixed;
   return a;
@@ -585,7 +585,9 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     if (const char* ev = std::getenv("SBFEM_DENSE8")) m->walsh = std::atoi(ev) == 0;
     bool ok = false;
     for (int32_t tn = tn0; tn >= 32; tn /= 2) {
-      if (sbfem::build_owner_tiles(ti, tn, to) && 24 * (to.max_local + to.tile_nodes) <= lds_max) {
+      const int64_t vbytes = d->prod == SBFEM_PROD_FP32 ? 4 : 8;
+      if (sbfem::build_owner_tiles(ti, tn, to) && 3 * vbytes * to.max_local + 24 * to.tile_nodes <= lds_max) {
+        m->lds_bytes = (int32_t)(3 * vbytes * to.max_local + 24 * to.tile_nodes);
         ok = true;
         break;
       }
@@ -602,7 +604,6 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     m->layout[3] = (int64_t)to.nodelist.size() + N;
     m->layout[4] = (int64_t)to.orient.size();
     m->layout[5] = to.tile_nodes;
-    m->lds_doubles = (int32_t)(3 * (to.max_local + to.tile_nodes));
     ALLOC(otiles, to.tiles.size())
     ALLOC(items, to.items.size())
     ALLOC(lidx, to.lidx.size())

@@ -15,6 +15,19 @@
 
 namespace sbfem {
 
+template <bool FP32>
+struct LdsType {
+  using T = double;
+};
+template <>
+struct LdsType<true> {
+  using T = float;
+};
+
+template <typename T>
+__device__ __forceinline__ T pick3t(int i, T x, T y, T z) {
+  return i == 0 ? x : (i == 1 ? y : z);
+}
 
 // The regular 8-node cell is symmetric under the three mirror planes, so in the
 // basis of Walsh functions over its corners (per displacement component) its
@@ -70,8 +83,10 @@ __device__ __forceinline__ void walsh8_apply(const T* __restrict__ W, const T (&
 
 template <int NN, bool FP32, int WALSH = 0>  // WALSH: 0 runtime choice, 1 always (8-node only)
 __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it, int lane, int n_own,
-                                          const double* __restrict__ ul, double* __restrict__ fl) {
+                                          const typename LdsType<FP32>::T* __restrict__ ul,
+                                          double* __restrict__ fl) {
   constexpr int ND = 3 * NN;
+  using T = typename LdsType<FP32>::T;
   const int64_t cell = it.cell0 + lane;
   int p0, p1, p2;
   double s0, s1, s2;
@@ -81,98 +96,67 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
 #pragma unroll
   for (int k = 0; k < NN; ++k) li[k] = a.lidx[it.lidx0 + (int64_t)k * it.count + lane];
   const uint32_t mask = it.mask;
-  if constexpr (!FP32) {
-    double ue[ND];
+  // oriented nodal displacements; the FP32 path also removes the rigid translation of
+  // node 0 (K_p annihilates it) so that only differences across the cell are rounded
+  T ue[ND];
+  {
+    T rx = 0, ry = 0, rz = 0;
+    if constexpr (FP32) {
+      const T* q0 = ul + 3 * li[0];
+      rx = q0[0];
+      ry = q0[1];
+      rz = q0[2];
+    }
 #pragma unroll
     for (int k = 0; k < NN; ++k) {
-      const double* q = ul + 3 * li[k];
-      const double x = q[0], y = q[1], z = q[2];
-      ue[3 * k + 0] = s0 * pick3(p0, x, y, z);
-      ue[3 * k + 1] = s1 * pick3(p1, x, y, z);
-      ue[3 * k + 2] = s2 * pick3(p2, x, y, z);
+      const T* q = ul + 3 * li[k];
+      const T x = q[0] - rx, y = q[1] - ry, z = q[2] - rz;
+      ue[3 * k + 0] = (T)s0 * pick3t<T>(p0, x, y, z);
+      ue[3 * k + 1] = (T)s1 * pick3t<T>(p1, x, y, z);
+      ue[3 * k + 2] = (T)s2 * pick3t<T>(p2, x, y, z);
     }
-    if constexpr (NN == 8) {
-      if (WALSH == 1 || it.koff == a.walsh_koff) {  // uniform in the wave
-        double fe[24];
-        walsh8_apply<double>(a.W64, ue, fe);
+  }
+  if constexpr (NN == 8) {
+    if (WALSH == 1 || it.koff == a.walsh_koff) {  // uniform in the wave
+      T fe[24];
+      walsh8_apply<T>(FP32 ? (const T*)a.W32 : (const T*)a.W64, ue, fe);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (!((mask >> k) & 1u)) continue;
-          if (li[k] >= n_own) continue;
-          atomicAdd(fl + 3 * li[k] + p0, s0 * se * fe[3 * k + 0]);
-          atomicAdd(fl + 3 * li[k] + p1, s1 * se * fe[3 * k + 1]);
-          atomicAdd(fl + 3 * li[k] + p2, s2 * se * fe[3 * k + 2]);
-        }
-        return;
+      for (int k = 0; k < 8; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        if (li[k] >= n_own) continue;
+        // forces are summed in FP64 (LDS FP64 atomics are also the fast ones here)
+        atomicAdd(fl + 3 * li[k] + p0, s0 * se * (double)fe[3 * k + 0]);
+        atomicAdd(fl + 3 * li[k] + p1, s1 * se * (double)fe[3 * k + 1]);
+        atomicAdd(fl + 3 * li[k] + p2, s2 * se * (double)fe[3 * k + 2]);
       }
+      return;
     }
-    if constexpr (WALSH == 1) return;
-    const double* Kp = a.K64 + it.koff;
+  }
+  if constexpr (WALSH == 1) return;
+  const T* Kp = FP32 ? (const T*)(a.K32 + it.koff) : (const T*)(a.K64 + it.koff);
 #pragma unroll
-    for (int k = 0; k < NN; ++k) {
-      if (!((mask >> k) & 1u)) continue;  // uniform in the wave
-      const bool own = li[k] < n_own;
+  for (int k = 0; k < NN; ++k) {
+    if (!((mask >> k) & 1u)) continue;  // uniform in the wave
+    const bool own = li[k] < n_own;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int i = 3 * k + c;
-        double acc = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const int i = 3 * k + c;
+      T acc = 0;
 #pragma unroll
-        for (int j = 0; j < ND; ++j) acc = fma(Kp[i * ND + j], ue[j], acc);
-        const int pc = c == 0 ? p0 : (c == 1 ? p1 : p2);
-        const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
-        if (own) atomicAdd(fl + 3 * li[k] + pc, sc * se * acc);
-      }
-    }
-  } else {
-    const double* q0 = ul + 3 * li[0];
-    const double rx = q0[0], ry = q0[1], rz = q0[2];
-    float ue[ND];
-#pragma unroll
-    for (int k = 0; k < NN; ++k) {
-      const double* q = ul + 3 * li[k];
-      const double x = q[0] - rx, y = q[1] - ry, z = q[2] - rz;
-      ue[3 * k + 0] = (float)(s0 * pick3(p0, x, y, z));
-      ue[3 * k + 1] = (float)(s1 * pick3(p1, x, y, z));
-      ue[3 * k + 2] = (float)(s2 * pick3(p2, x, y, z));
-    }
-    if constexpr (NN == 8) {
-      if (WALSH == 1 || it.koff == a.walsh_koff) {
-        float fe[24];
-        walsh8_apply<float>(a.W32, ue, fe);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (!((mask >> k) & 1u)) continue;
-          if (li[k] >= n_own) continue;
-          atomicAdd(fl + 3 * li[k] + p0, s0 * se * (double)fe[3 * k + 0]);
-          atomicAdd(fl + 3 * li[k] + p1, s1 * se * (double)fe[3 * k + 1]);
-          atomicAdd(fl + 3 * li[k] + p2, s2 * se * (double)fe[3 * k + 2]);
-        }
-        return;
-      }
-    }
-    if constexpr (WALSH == 1) return;
-    const float* Kp = a.K32 + it.koff;
-#pragma unroll
-    for (int k = 0; k < NN; ++k) {
-      if (!((mask >> k) & 1u)) continue;
-      const bool own = li[k] < n_own;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int i = 3 * k + c;
-        float acc = 0.0f;
-#pragma unroll
-        for (int j = 0; j < ND; ++j) acc = fmaf(Kp[i * ND + j], ue[j], acc);
-        const int pc = c == 0 ? p0 : (c == 1 ? p1 : p2);
-        const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
-        if (own) atomicAdd(fl + 3 * li[k] + pc, sc * se * (double)acc);
-      }
+      for (int j = 0; j < ND; ++j) acc = fma(Kp[i * ND + j], ue[j], acc);
+      const int pc = c == 0 ? p0 : (c == 1 ? p1 : p2);
+      const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
+      if (own) atomicAdd(fl + 3 * li[k] + pc, sc * se * (double)acc);
     }
   }
 }
 
 // PURE8: tiles of 8-node cells only; WALSH (with PURE8): use the block form of the 8-node matrix.
+// LDS holds the owned forces (FP64) and u of the local nodes: FP64 for FP64 products, and for
+// FP32 products u minus the displacement of the tile's first owned node, in FP32.
 template <bool PURE8, bool FP32, bool WALSH = false>
 __global__ void __launch_bounds__(512) tiled_step(TiledArgs a, int64_t first, int64_t count, int force_only) {
+  using T = typename LdsType<FP32>::T;
   extern __shared__ double lds[];
   // XCD-contiguous block -> tile map
   const int64_t per = (count + 7) / 8;
@@ -181,16 +165,21 @@ __global__ void __launch_bounds__(512) tiled_step(TiledArgs a, int64_t first, in
   if (t >= count) return;
   const OwnerTile tile = a.tiles[first + t];
   const int n_own = tile.n_own, n_local = tile.n_local;
-  double* ul = lds;
-  double* fl = lds + 3 * (int64_t)n_local;
+  double* fl = lds;
+  T* ul = (T*)(lds + 3 * (int64_t)n_own);
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
+  double ref[3] = {0.0, 0.0, 0.0};
+  if constexpr (FP32) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ref[c] = a.u[3 * tile.own0 + c];
+  }
   for (int i = tid; i < 3 * n_local; i += nt) {
     const int l = i / 3, c = i - 3 * l;
     const int64_t g = l < n_own ? tile.own0 + l : (int64_t)a.nodelist[tile.node0 + l - n_own];
-    ul[i] = a.u[3 * g + c];
+    ul[i] = (T)(a.u[3 * g + c] - ref[c]);
   }
-  for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0.0;
+  for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0;
   __syncthreads();
   if (!force_only)
     for (int i = tid; i < tile.n_load; i += nt) {
@@ -229,7 +218,8 @@ __global__ void __launch_bounds__(512) tiled_step(TiledArgs a, int64_t first, in
     const double inv = 1.0 / (1.0 + a.c);
     for (int i = tid; i < 3 * n_own; i += nt) {
       const int64_t d = d0 + i;
-      a.um1[d] = (a.dt2 * a.minv[d] * (-fl[i]) + 2.0 * ul[i] - (1.0 - a.c) * a.um1[d]) * inv;
+      const double un = FP32 ? a.u[d] : (double)ul[i];  // FP32 staging holds differences only
+      a.um1[d] = (a.dt2 * a.minv[d] * (-fl[i]) + 2.0 * un - (1.0 - a.c) * a.um1[d]) * inv;
     }
   }
 }
