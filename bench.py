@@ -12,7 +12,15 @@ is the FP32-product / FP64-state path; the plain FP64 path (and the colour
 assembly) are timed beside it.  A second, event-instrumented pass gives the
 average duration per launch of each kernel class for the roofline figure.
 
+Serving (reported beside the throughput): a Poisson stream of 256 requests
+(mean 20/s) of seeded inclusion meshes of 1e4-5e6 dofs (log-uniform) with
+200-3000 steps each, built before the clock.  Requests are admitted in
+arrival order while their device footprint fits a 4 GB budget, then again
+with the whole free HBM; p50/p99 latency is arrival -> result on the host.
+A seeded subset is re-run alone and compared with its served result.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg3|cfg2]
+                       [--serve N] [--serve-only]
 """
 
 import argparse
@@ -115,6 +123,65 @@ def cpu_baseline(seconds=12.0):
                        f"{n} steps in {el:.1f} s")
 
 
+def serving(torch, args):
+    """The request stream served twice (memory budget, then the free HBM)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from meshgen import configs
+    from paper_2103_09100_amd.serve import Request, Server, latency_stats, link_cells
+    from paper_2103_09100_amd.solver import Simulation, device_patterns
+
+    specs = configs.serving_requests(seed=5, n=args.serve)
+    t0 = time.time()
+
+    def make(i):
+        sp = specs[i]
+        r = Request(i, configs.request_mesh(sp["seed"], sp["target_dof"], sp["n_steps"]), sp["n_steps"],
+                    sp["arrival"])
+        r.mesh.node_lat = None
+        return link_cells(r)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        reqs = list(ex.map(make, range(len(specs))))
+    total = sum(r.mesh.n_dof * r.n_steps for r in reqs)
+    log(f"[serve] {len(reqs)} requests built and linked in {time.time() - t0:.0f} s: "
+        f"{sum(r.mesh.n_dof for r in reqs) / 1e6:.1f} M dofs, {total:.3e} dof-steps, "
+        f"arrivals over {reqs[-1].arrival:.1f} s")
+    device_patterns(reqs[0].mesh.nu)
+    st, st2 = torch.cuda.Stream(), torch.cuda.Stream()
+    free = torch.cuda.mem_get_info()[0]
+    out = {}
+    for label, budget in (("budget", int(args.serve_budget_gb * 1e9)), ("full_hbm", int(0.9 * free))):
+        for r in reqs:
+            r.reset()
+        srv = Server(budget_bytes=budget, quantum=args.serve_quantum, prod=args.serve_prod,
+                     stream=st.cuda_stream, setup_stream=st2.cuda_stream)
+        t1 = time.time()
+        srv.run(reqs)
+        stats = latency_stats(reqs)
+        stats.update(budget_bytes=budget, wall_s=time.time() - t1,
+                     queue_p50_s=float(np.percentile([r.admitted - r.arrival for r in reqs], 50)),
+                     queue_p99_s=float(np.percentile([r.admitted - r.arrival for r in reqs], 99)))
+        out[label] = stats
+        log(f"[serve] {label} ({budget / 1e9:.1f} GB): p50 {stats['p50_s']:.3f} s, p99 {stats['p99_s']:.3f} s, "
+            f"{stats['dof_steps_per_s']:.3e} dof-steps/s over {stats['span_s']:.1f} s")
+    # a seeded subset, each run alone, against its served result (last run)
+    pick = np.random.default_rng(5).choice(len(reqs), size=min(4, len(reqs)), replace=False)
+    worst = 0.0
+    for i in pick:
+        r = reqs[i]
+        sim = Simulation(r.mesh, prod=args.serve_prod, stream=st.cuda_stream)
+        sim.step(r.n_steps)
+        alone = sim.u()
+        sim.close()
+        worst = max(worst, float(np.abs(r.result - alone).max() / max(np.abs(alone).max(), 1e-300)))
+    out.update(requests=len(reqs), product=args.serve_prod, state="fp64", quantum=args.serve_quantum,
+               dof_steps=float(total), alone_vs_served_max_rel=worst, alone_checked=[int(i) for i in pick],
+               workload="Poisson stream (20/s) of seeded inclusion octrees, 1e4-5e6 dofs log-uniform, "
+                        "200-3000 steps, built before the clock")
+    log(f"[serve] alone vs served, requests {list(map(int, pick))}: max rel {worst:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +193,11 @@ def main():
                     help="assembly variants timed beside the headline over --compare-steps steps")
     ap.add_argument("--compare-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving stream")
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0)
+    ap.add_argument("--serve-quantum", type=int, default=50, help="steps per batched call")
+    ap.add_argument("--serve-prod", default="fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -137,6 +209,14 @@ def main():
     import torch
     from paper_2103_09100_amd import library
     from paper_2103_09100_amd.solver import Simulation
+
+    if args.serve_only:
+        sv = serving(torch, args)
+        print(json.dumps({"metric": "p99 solve latency (serving stream)", "value": sv["budget"]["p99_s"],
+                          "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+                          "dtype": args.serve_prod, "data": "synthetic",
+                          "config": {"workload": sv["workload"]}, "serving": sv}), flush=True)
+        return
 
     t0 = time.time()
     mesh, desc = make_mesh(args.config)
@@ -213,6 +293,9 @@ def main():
         out["speedup_vs_fp64"] = r["value"] / results[fp64]["value"]
         ref = finals[fp64]
         out["rel_err_vs_fp64"] = float(np.abs(finals[head] - ref).max() / np.abs(ref).max())
+    if args.serve > 0:
+        out["serving"] = serving(torch, args)
+        out["p99_latency_s"] = out["serving"]["budget"]["p99_s"]
     if not args.no_cpu:
         log("[bench] oracle baseline on the host")
         out["cpu_baseline"] = cpu_baseline()

@@ -94,6 +94,13 @@ typedef struct {
   int32_t assembly;             /* sbfem_asm */
   const double* u0;             /* host [3N] initial displacement, NULL = zero */
   const double* v0;             /* host [3N] initial velocity, NULL = zero */
+  /* owner-tile shape (TILED assembly); 0 = library default.  tile_nodes: nodes owned by one
+     block (halved automatically until the block's on-chip memory fits); block_threads:
+     threads per block for tiles of 8-node cells, block_threads_mixed for the others
+     (multiples of 64, at most 512). */
+  int32_t tile_nodes;
+  int32_t block_threads;
+  int32_t block_threads_mixed;
 } sbfem_mesh_desc;
 
 /*
@@ -138,9 +145,11 @@ void sbfem_destroy_mesh(sbfem_mesh* m);
 sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream);
 
 /*
- * Advance several meshes in one stream: mesh i takes n_steps[i] steps.  Steps
- * of different meshes are interleaved so that each launch covers every mesh
- * that still has steps to take.
+ * Advance several meshes in one stream: mesh i takes n_steps[i] steps (a mesh
+ * may appear once).  Owner-tile meshes that share a pattern library, product
+ * precision and block shape advance together: each launch covers the tiles of
+ * every such mesh that still has steps to take.  Other meshes are stepped in
+ * turn.  Returns after the work of the batched groups has completed.
  */
 sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream);
 

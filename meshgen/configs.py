@@ -265,10 +265,10 @@ def _ellipsoid_radius(x, ells, chunk=1 << 22):
     return out
 
 
-def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=1.05, keep_node_lat=True, nu=0.25):
+def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=1.05, keep_node_lat=True, nu=0.25, n_incl=3):
     """Ellipsoid-inclusion octree (cfg3 recipe): level lfine where the scaled
     ellipsoid radius is below 1+band, level lcoarse elsewhere; E=5, rho=2 inside."""
-    ells = ellipsoids(seed)
+    ells = ellipsoids(seed, n_incl)
 
     def refine(level, idx):
         h = 2.0 ** -level
@@ -352,3 +352,28 @@ def serving_requests(seed=5, n=256, rate=20.0, dof_lo=1e4, dof_hi=5e6):
     seeds = rng.integers(0, 2 ** 31 - 1, size=n)
     return [dict(arrival=float(a), target_dof=float(s), n_steps=int(k), seed=int(sd))
             for a, s, k, sd in zip(arrivals, sizes, steps, seeds)]
+
+
+def request_mesh(seed, target_dof, n_steps):
+    """A serving request: 1-3 seeded inclusions, two octree levels chosen so that the
+    mesh has roughly target_dof dofs, Ricker patch load with a seeded centre frequency
+    resolved by at least 10 coarse cells per shear wavelength."""
+    rng = np.random.default_rng([55, seed])
+    n_incl = int(rng.integers(1, 4))
+    nodes = target_dof / 3.0
+    lev = int(np.clip(np.round(np.log2(np.cbrt(nodes / 3.0))), 2, 8))
+    frac = float(np.clip((nodes / (2 ** lev + 1) ** 3 - 1.0) / 7.0, 0.02, 0.98))
+    # band giving that refined fraction on the coarse grid
+    ells = ellipsoids(seed, n_incl)
+    n = 1 << lev
+    g = (np.argwhere(np.ones((n, n, n), dtype=bool)) + 0.5) / n
+    r = np.sort(_ellipsoid_radius(g, ells))
+    band = max(float(r[min(len(r) - 1, int(frac * len(r)))]) - 1.0, 0.0)
+    m = inclusion_mesh(seed=seed, lcoarse=lev, lfine=lev + 1, band=band, n_incl=n_incl)
+    # Ricker centre frequency with at least 10 coarse cells per shear wavelength
+    # (c_s = sqrt(E / (2 (1 + nu) rho)) of the matrix material)
+    c_s = math.sqrt(1.0 / (2.0 * (1.0 + m.nu)))
+    fm = float(rng.uniform(0.5, 1.0)) * c_s / (10.0 / n)
+    _run_params(m, fm=fm, n_steps=n_steps)
+    m.meta.update(name=f"request seed {seed}", target_dof=target_dof)
+    return m

@@ -14,6 +14,7 @@ this project: a face gets a centre node unless it has no mid-edge node or
 exactly two on opposite edges (the two cases that tile by rectangles alone).
 """
 
+import threading
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -129,13 +130,21 @@ def refine_levels(roots, lmin, lmax, refine):
 
 
 _NATIVE = None
+# the native generator keeps one result between og_build and og_fetch: one caller at a time
+_NATIVE_LOCK = threading.Lock()
+_LOAD_LOCK = threading.Lock()
 
 
 def _native():
     """Load (building on first use) the native leaf/node/connectivity routine."""
     global _NATIVE
-    if _NATIVE is not None:
-        return _NATIVE
+    with _LOAD_LOCK:
+        if _NATIVE is None:
+            _NATIVE = _load_native()
+    return _NATIVE
+
+
+def _load_native():
     import ctypes
     import os
     import subprocess
@@ -148,7 +157,6 @@ def _native():
     P = ctypes.c_void_p
     L.og_build.argtypes = [P, ctypes.c_int, P, P]
     L.og_fetch.argtypes = [P, P, P, P, P, P]
-    _NATIVE = L
     return L
 
 
@@ -180,18 +188,19 @@ def build_mesh(roots, h0, lmin, lmax, refine, material=None, mat_E=(1.0,), mat_r
     ptrs = (ctypes.c_void_p * max(1, len(refined)))(*[r.ctypes.data for r in refined])
     rts = np.array(roots, dtype=np.int64)
     counts = np.zeros(3, dtype=np.int64)
-    if L.og_build(rts.ctypes.data, int(lmax), ptrs, counts.ctypes.data) != 0:
-        raise RuntimeError("octree generation failed")
-    del refined
-    C, n_nodes, n_conn = (int(v) for v in counts)
-    cell_level = np.empty(C, dtype=np.uint8)
-    cell_lat = np.empty((C, 3), dtype=np.int32)
-    cell_slots = np.empty(C, dtype=np.uint32)
-    conn_ptr = np.empty(C + 1, dtype=np.int64)
-    conn = np.empty(n_conn, dtype=np.int32)
-    node_lat = np.empty((n_nodes, 3), dtype=np.int32)
-    L.og_fetch(cell_level.ctypes.data, cell_lat.ctypes.data, cell_slots.ctypes.data,
-               conn_ptr.ctypes.data, conn.ctypes.data, node_lat.ctypes.data)
+    with _NATIVE_LOCK:
+        if L.og_build(rts.ctypes.data, int(lmax), ptrs, counts.ctypes.data) != 0:
+            raise RuntimeError("octree generation failed")
+        del refined
+        C, n_nodes, n_conn = (int(v) for v in counts)
+        cell_level = np.empty(C, dtype=np.uint8)
+        cell_lat = np.empty((C, 3), dtype=np.int32)
+        cell_slots = np.empty(C, dtype=np.uint32)
+        conn_ptr = np.empty(C + 1, dtype=np.int64)
+        conn = np.empty(n_conn, dtype=np.int32)
+        node_lat = np.empty((n_nodes, 3), dtype=np.int32)
+        L.og_fetch(cell_level.ctypes.data, cell_lat.ctypes.data, cell_slots.ctypes.data,
+                   conn_ptr.ctypes.data, conn.ctypes.data, node_lat.ctypes.data)
 
     full = np.int64(1) << (lmax - cell_level.astype(np.int64))
     if material is None:

@@ -16,6 +16,16 @@ LIB_PATH = os.path.join(HERE, "libsbfem.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_09100_amd.build`")
 
+# One HIP runtime per process.  The PyTorch wheel carries its own HIP and HSA runtimes
+# whose sonames equal the system ones; loaded after torch, the library binds to torch's
+# copy, so streams and device pointers handed over from torch are valid here.  Loaded
+# first, it would pull in the system copy and torch would then start a second runtime
+# that finds no device.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY = 0, -1, -2, -3, -4, -5
@@ -44,6 +54,7 @@ class MeshDesc(C.Structure):
         ("dt", C.c_double), ("alpha", C.c_double),
         ("prod", C.c_int32), ("state", C.c_int32), ("assembly", C.c_int32),
         ("u0", C.c_void_p), ("v0", C.c_void_p),
+        ("tile_nodes", C.c_int32), ("block_threads", C.c_int32), ("block_threads_mixed", C.c_int32),
     ]
 
 
@@ -122,7 +133,7 @@ class Patterns:
 
 
 def make_desc(mesh, pid, orient, conn, dt, prod="fp64", state="fp64", assembly="atomic",
-              u0=None, v0=None):
+              u0=None, v0=None, tile_nodes=0, block_threads=0, block_threads_mixed=0):
     """Descriptor (plus the arrays it points into) for a canonicalised mesh."""
     keep = dict(
         conn=np.ascontiguousarray(conn, dtype=np.int32),
@@ -166,6 +177,9 @@ def make_desc(mesh, pid, orient, conn, dt, prod="fp64", state="fp64", assembly="
     d.assembly = ASM[assembly]
     d.u0 = _ptr(keep["u0"])
     d.v0 = _ptr(keep["v0"])
+    d.tile_nodes = int(tile_nodes)
+    d.block_threads = int(block_threads)
+    d.block_threads_mixed = int(block_threads_mixed)
     return d, keep
 
 

@@ -9,6 +9,13 @@ namespace sbfem {
 constexpr int kTile = 256;  // cells per block (one cell per thread)
 constexpr int kWave = 64;
 
+struct LoadParams {
+  int32_t kind;
+  int32_t cycles;
+  double t1;
+  double P0;
+};
+
 // Owner tile: a block updates the nodes [own0, own0 + n_own) (internal ids).
 // Its local nodes are the owned ones (local i < n_own is node own0 + i) followed
 // by the other nodes its cells touch (local i >= n_own is nodelist[node0 + i - n_own]);
@@ -63,7 +70,8 @@ struct TiledArgs {
   double* um1;          // u_{n-1} in, u_{n+1} out (owned nodes)
   const double* minv;
   double* f;            // force-only mode: R_int of owned dofs written here
-  double P;             // P(t_n)
+  LoadParams L;         // P(t) of the load vector
+  double dt;
   double dt2;
   double c;             // alpha dt / 2
   int32_t lds_bytes;    // dynamic LDS: 3 FP64 forces per owned node + 3 u values per local node
@@ -86,13 +94,6 @@ struct TileRange {
   int64_t first;
   int64_t n_fixed8;
   int64_t n_mixed;
-};
-
-struct LoadParams {
-  int32_t kind;
-  int32_t cycles;
-  double t1;
-  double P0;
 };
 
 struct ElementArgs {
@@ -120,17 +121,45 @@ struct LaunchHook {
 
 hipError_t launch_ebe(const ElementArgs& a, const TileRange& r, bool fp32, bool atomic, hipStream_t s,
                       const LaunchHook& hook = LaunchHook());
-// One time step over owner tiles (tiles [0, n_pure8) hold 8-node cells only, the next
-// n_mixed any pattern).  force_only: write R_int of the owned dofs to a.f instead of updating.
-hipError_t launch_tiled(const TiledArgs& a, int64_t n_pure8, int64_t n_mixed, bool fp32, bool force_only,
-                        hipStream_t s, const LaunchHook& hook = LaunchHook());
+// A mesh in a tiled launch: its two argument blocks (u and u_prev swap roles every step),
+// the step number of the launch and which block holds the current roles.
+struct MeshRef {
+  const TiledArgs* args;  // device, 2 entries
+  int64_t step;
+  int32_t parity;
+  int32_t pad;
+};
+// (mesh, tile) of a batched launch
+struct TileWork {
+  int32_t mesh;
+  int32_t pad;
+  int64_t tile;
+};
+
+// Launch description: either one mesh (single, work == nullptr; tiles [0, n_pure8) of
+// 8-node cells only, then n_mixed others) or a batch (refs + work lists).
+struct TiledLaunch {
+  MeshRef single;
+  const MeshRef* refs = nullptr;
+  const TileWork* work8 = nullptr;     // batch: 8-node-only tiles of every mesh
+  const TileWork* work_mixed = nullptr;
+  int64_t n_pure8 = 0, n_mixed = 0;
+  int64_t k = 0;                       // batch: steps since the refs were recorded
+  bool fp32 = false;
+  bool walsh = false;
+  bool force_only = false;
+  int32_t threads8 = 512, threads_mixed = 256;
+  size_t lds = 0;
+};
+
+hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& hook = LaunchHook());
 // per-unit launchers
 void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, bool atomic, hipStream_t s);
 void ebe_mixed_fp64_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
 void ebe_mixed_fp32_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
-void tiled_pure8_launch(const TiledArgs& a, int64_t first, int64_t count, bool fp32, bool force_only, hipStream_t s);
-void tiled_mixed_fp64_launch(const TiledArgs& a, int64_t first, int64_t count, bool force_only, hipStream_t s);
-void tiled_mixed_fp32_launch(const TiledArgs& a, int64_t first, int64_t count, bool force_only, hipStream_t s);
+void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_mixed_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_mixed_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 
 hipError_t launch_load(double* f, const int64_t* idx, const double* val, int64_t nnz, const LoadParams& L,
                        double t, hipStream_t s);

@@ -110,21 +110,21 @@ hipError_t launch_finite(const double* a, int64_t n, int32_t* flag, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_tiled(const TiledArgs& a, int64_t n_pure8, int64_t n_mixed, bool fp32, bool force_only,
-                        hipStream_t s, const LaunchHook& hook) {
-  if (n_pure8 > 0) {
+hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& hook) {
+  const bool batch = L.refs != nullptr;
+  if (L.n_pure8 > 0) {
     hook(1, true, s);
-    tiled_pure8_launch(a, 0, n_pure8, fp32, force_only, s);
+    tiled_pure8_launch(L, batch ? L.work8 : nullptr, 0, L.n_pure8, s);
     hook(1, false, s);
   }
-  if (n_mixed > 0) {
+  if (L.n_mixed > 0) {
     hook(2, true, s);
-    TiledArgs b = a;
-    b.block_threads = a.block_threads_mixed;
-    if (fp32)
-      tiled_mixed_fp32_launch(b, n_pure8, n_mixed, force_only, s);
+    const TileWork* w = batch ? L.work_mixed : nullptr;
+    const int64_t first = batch ? 0 : L.n_pure8;
+    if (L.fp32)
+      tiled_mixed_fp32_launch(L, w, first, L.n_mixed, s);
     else
-      tiled_mixed_fp64_launch(b, n_pure8, n_mixed, force_only, s);
+      tiled_mixed_fp64_launch(L, w, first, L.n_mixed, s);
     hook(2, false, s);
   }
   return hipGetLastError();
@@ -144,23 +144,20 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 }
 
 // 8-node owner tiles
-void tiled_pure8_launch(const TiledArgs& a, int64_t first, int64_t count, bool fp32, bool force_only,
-                        hipStream_t s) {
+void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
-  const size_t lds = (size_t)a.lds_bytes;
-  const bool walsh = a.walsh_koff >= 0;
-#define SBFEM_L(F, W)                                                                                    \
-  do {                                                                                                   \
-    if (lds > 65536)                                                                                     \
-      (void)hipFuncSetAttribute((const void*)tiled_step<true, F, W>,                                     \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                   \
-    hipLaunchKernelGGL((tiled_step<true, F, W>), dim3((unsigned)blocks), dim3(a.block_threads), lds, s, a, \
-                       first, count, (int)force_only);                                                   \
+#define SBFEM_L(F, W)                                                                                         \
+  do {                                                                                                        \
+    if (L.lds > 65536)                                                                                        \
+      (void)hipFuncSetAttribute((const void*)tiled_step<true, F, W>,                                          \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds);                      \
+    hipLaunchKernelGGL((tiled_step<true, F, W>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, \
+                       L.refs, work, first, count, L.k, (int)L.force_only);                                        \
   } while (0)
-  if (fp32) {
-    if (walsh) SBFEM_L(true, true); else SBFEM_L(true, false);
+  if (L.fp32) {
+    if (L.walsh) SBFEM_L(true, true); else SBFEM_L(true, false);
   } else {
-    if (walsh) SBFEM_L(false, true); else SBFEM_L(false, false);
+    if (L.walsh) SBFEM_L(false, true); else SBFEM_L(false, false);
   }
 #undef SBFEM_L
 }

@@ -3,14 +3,14 @@
 
 namespace sbfem {
 
-void tiled_mixed_fp64_launch(const TiledArgs& a, int64_t first, int64_t count, bool force_only, hipStream_t s) {
+void tiled_mixed_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count,
+                             hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
-  const size_t lds = (size_t)a.lds_bytes;
-  if (lds > 65536)
+  if (L.lds > 65536)
     (void)hipFuncSetAttribute((const void*)tiled_step<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-  hipLaunchKernelGGL((tiled_step<false, false>), dim3((unsigned)blocks), dim3(a.block_threads), lds, s, a, first,
-                     count, (int)force_only);
+                              (int)L.lds);
+  hipLaunchKernelGGL((tiled_step<false, false>), dim3((unsigned)blocks), dim3(L.threads_mixed), L.lds, s, L.single,
+                     L.refs, work, first, count, L.k, (int)L.force_only);
 }
 
 }  // namespace sbfem

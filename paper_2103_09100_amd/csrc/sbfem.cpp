@@ -143,6 +143,8 @@ struct sbfem_mesh {
   sbfem::LoadEntry* tloads = nullptr;
   int64_t n_pure8 = 0, n_mixed = 0;
   int32_t lds_bytes = 0;
+  sbfem::TiledArgs* d_args = nullptr;   // two argument blocks: (u=buf0, prev=buf1) and swapped
+  double* buf0 = nullptr;
   int32_t block_threads = 512;        // 8-node owner tiles
   int32_t block_threads_mixed = 256;  // owner tiles with larger cells
   bool walsh = true;
@@ -173,6 +175,10 @@ sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
   if (d->state != SBFEM_STATE_FP64) return fail(SBFEM_EINVAL, "state storage %d not available", d->state);
   if (d->assembly != SBFEM_ASM_ATOMIC && d->assembly != SBFEM_ASM_COLOUR && d->assembly != SBFEM_ASM_TILED)
     return fail(SBFEM_EINVAL, "unknown assembly mode");
+  if (d->tile_nodes < 0 || d->block_threads < 0 || d->block_threads_mixed < 0 ||
+      (d->block_threads && (d->block_threads % 64 || d->block_threads > 512)) ||
+      (d->block_threads_mixed && (d->block_threads_mixed % 64 || d->block_threads_mixed > 512)))
+    return fail(SBFEM_EINVAL, "bad owner-tile shape");
   for (int64_t c = 0; c < d->n_cells; ++c) {
     if (d->pattern[c] >= p->n) return fail(SBFEM_EINVAL, "cell %lld: pattern %d out of range", (long long)c, d->pattern[c]);
     if (d->orient[c] >= 48) return fail(SBFEM_EINVAL, "cell %lld: orientation %d >= 48", (long long)c, d->orient[c]);
@@ -349,6 +355,7 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->lidx);
   dfree(m->nodelist);
   dfree(m->tloads);
+  dfree(m->d_args);
   delete m;
 }
 
@@ -389,7 +396,7 @@ static sbfem::LaunchHook hook_of(sbfem_mesh* m) {
 }
 
 // f += R_int(u) over all colours (f must hold what it should be added to)
-static sbfem::TiledArgs tiled_args(sbfem_mesh* m) {
+static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const double* u, double* um1) {
   sbfem::TiledArgs a{};
   a.tiles = m->otiles;
   a.n_tiles = m->n_pure8 + m->n_mixed;
@@ -407,10 +414,12 @@ static sbfem::TiledArgs tiled_args(sbfem_mesh* m) {
   a.W64 = m->P->dW64;
   a.W32 = m->P->dW32;
   a.walsh_koff = m->walsh ? m->P->walsh_koff : -1;
-  a.u = m->u;
-  a.um1 = m->um1;
+  a.u = u;
+  a.um1 = um1;
   a.minv = m->minv;
   a.f = m->f;
+  a.L = m->L;
+  a.dt = m->dt;
   a.dt2 = m->dt * m->dt;
   a.c = 0.5 * m->alpha * m->dt;
   a.lds_bytes = m->lds_bytes;
@@ -419,10 +428,27 @@ static sbfem::TiledArgs tiled_args(sbfem_mesh* m) {
   return a;
 }
 
+static int tiled_parity(const sbfem_mesh* m) { return m->u == m->buf0 ? 0 : 1; }
+
+static sbfem::TiledLaunch tiled_launch(const sbfem_mesh* m, bool force_only) {
+  sbfem::TiledLaunch L;
+  L.single.args = m->d_args;
+  L.single.step = m->step;
+  L.single.parity = tiled_parity(m);
+  L.n_pure8 = m->n_pure8;
+  L.n_mixed = m->n_mixed;
+  L.fp32 = m->prod == SBFEM_PROD_FP32;
+  L.walsh = m->walsh && m->P->walsh_koff >= 0;
+  L.force_only = force_only;
+  L.threads8 = m->block_threads;
+  L.threads_mixed = m->block_threads_mixed;
+  L.lds = (size_t)m->lds_bytes;
+  return L;
+}
+
 static sbfem_status internal_force(sbfem_mesh* m, hipStream_t s) {
   if (m->assembly == SBFEM_ASM_TILED) {
-    sbfem::TiledArgs a = tiled_args(m);
-    HIP_TRY(sbfem::launch_tiled(a, m->n_pure8, m->n_mixed, m->prod == SBFEM_PROD_FP32, true, s, hook_of(m)));
+    HIP_TRY(sbfem::launch_tiled(tiled_launch(m, true), s, hook_of(m)));
     return SBFEM_OK;
   }
   sbfem::ElementArgs a = element_args(m);
@@ -582,6 +608,13 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     };
     threads_env("SBFEM_BLOCK_THREADS", m->block_threads);
     threads_env("SBFEM_BLOCK_THREADS_MIXED", m->block_threads_mixed);
+    // explicit descriptor values win over the defaults and the environment
+    auto threads_desc = [](int32_t v, int32_t& out) {
+      if (v >= 64 && v <= 512 && v % 64 == 0) out = v;
+    };
+    threads_desc(d->block_threads, m->block_threads);
+    threads_desc(d->block_threads_mixed, m->block_threads_mixed);
+    if (d->tile_nodes > 0) tn0 = std::max(32, d->tile_nodes);
     if (const char* ev = std::getenv("SBFEM_DENSE8")) m->walsh = std::atoi(ev) == 0;
     bool ok = false;
     for (int32_t tn = tn0; tn >= 32; tn /= 2) {
@@ -612,6 +645,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     ALLOC(orient, to.orient.size())
     ALLOC(level, to.level.size())
     ALLOC(material, to.material.size())
+    ALLOC(d_args, 2)
     H2D(m->otiles, to.tiles.data(), to.tiles.size() * sizeof(sbfem::OwnerTile));
     H2D(m->items, to.items.data(), to.items.size() * sizeof(sbfem::CellItem));
     H2D(m->lidx, to.lidx.data(), to.lidx.size() * 2);
@@ -728,6 +762,12 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
                 hipGetErrorString(e));
   }
   *m->flag_h = 0;
+  m->buf0 = m->u;
+  if (d->assembly == SBFEM_ASM_TILED) {
+    const sbfem::TiledArgs ta[2] = {tiled_args_for(m, m->u, m->um1), tiled_args_for(m, m->um1, m->u)};
+    H2D(m->d_args, ta, sizeof(ta));
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
 
   // start-up point (eq. D0): u_-1 = u0 - dt v0 + dt^2/2 a0,  a0 = M^-1 (P(0) b - K u0) - alpha v0
   std::vector<double> u0(ndof, 0.0), v0(ndof, 0.0), ku0(ndof, 0.0);
@@ -781,9 +821,8 @@ static sbfem_status enqueue_step(sbfem_mesh* m, hipStream_t s) {
   const double t = (double)m->step * m->dt;
   const sbfem::LaunchHook h = hook_of(m);
   if (m->assembly == SBFEM_ASM_TILED) {
-    sbfem::TiledArgs a = tiled_args(m);
-    a.P = load_time_host(m->L, t);
-    HIP_TRY(sbfem::launch_tiled(a, m->n_pure8, m->n_mixed, m->prod == SBFEM_PROD_FP32, false, s, h));
+    (void)t;
+    HIP_TRY(sbfem::launch_tiled(tiled_launch(m, false), s, h));
     std::swap(m->u, m->um1);
     m->step++;
     return SBFEM_OK;
@@ -824,24 +863,123 @@ sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream) {
   return SBFEM_OK;
 }
 
+// Owner-tile meshes that share a pattern library and a product precision advance together:
+// one launch per step and tile class covers the tiles of every mesh that still has steps
+// to take (work lists rebuilt when a mesh finishes).  Other meshes step one by one.
+static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::vector<int64_t>& steps,
+                                hipStream_t s) {
+  const size_t n = g.size();
+  std::vector<sbfem::MeshRef> refs(n);
+  for (size_t i = 0; i < n; ++i) {
+    refs[i].args = g[i]->d_args;
+    refs[i].step = g[i]->step;
+    refs[i].parity = tiled_parity(g[i]);
+    refs[i].pad = 0;
+  }
+  int64_t tot8 = 0, totm = 0, most = 0;
+  for (size_t i = 0; i < n; ++i) {
+    tot8 += g[i]->n_pure8;
+    totm += g[i]->n_mixed;
+    most = std::max(most, steps[i]);
+  }
+  sbfem::MeshRef* d_refs = nullptr;
+  sbfem::TileWork *d_w8 = nullptr, *d_wm = nullptr;
+  HIP_TRY(hipMalloc((void**)&d_refs, n * sizeof(sbfem::MeshRef)));
+  hipError_t e = hipMalloc((void**)&d_w8, std::max<int64_t>(1, tot8) * sizeof(sbfem::TileWork));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_wm, std::max<int64_t>(1, totm) * sizeof(sbfem::TileWork));
+  if (e == hipSuccess) e = hipMemcpyAsync(d_refs, refs.data(), n * sizeof(sbfem::MeshRef), hipMemcpyHostToDevice, s);
+  std::vector<sbfem::TileWork> w8, wm;
+  std::vector<size_t> done(n, 0);
+  int64_t built_for = -1;
+  sbfem::TiledLaunch L = tiled_launch(g[0], false);
+  L.refs = d_refs;
+  L.work8 = d_w8;
+  L.work_mixed = d_wm;
+  size_t lds = 0;
+  for (auto* m : g) lds = std::max(lds, (size_t)m->lds_bytes);
+  L.lds = lds;
+  for (int64_t k = 0; k < most && e == hipSuccess; ++k) {
+    // active set changes only when a mesh runs out of steps
+    bool change = built_for < 0;
+    for (size_t i = 0; i < n; ++i)
+      if (steps[i] == k && k > 0) change = true;
+    if (change) {
+      if (built_for >= 0) e = hipStreamSynchronize(s);  // previous lists are in use until here
+      w8.clear();
+      wm.clear();
+      for (size_t i = 0; i < n; ++i) {
+        if (k >= steps[i]) continue;
+        for (int64_t t = 0; t < g[i]->n_pure8; ++t) w8.push_back({(int32_t)i, 0, t});
+        for (int64_t t = 0; t < g[i]->n_mixed; ++t) wm.push_back({(int32_t)i, 0, g[i]->n_pure8 + t});
+      }
+      if (e == hipSuccess && !w8.empty())
+        e = hipMemcpyAsync(d_w8, w8.data(), w8.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess && !wm.empty())
+        e = hipMemcpyAsync(d_wm, wm.data(), wm.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
+      built_for = k;
+    }
+    L.k = k;
+    L.n_pure8 = (int64_t)w8.size();
+    L.n_mixed = (int64_t)wm.size();
+    if (e == hipSuccess) e = sbfem::launch_tiled(L, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_refs);
+  (void)hipFree(d_w8);
+  (void)hipFree(d_wm);
+  if (e != hipSuccess) return fail(SBFEM_EDEVICE, "batched step: %s", hipGetErrorString(e));
+  for (size_t i = 0; i < n; ++i) {
+    if (steps[i] & 1) std::swap(g[i]->u, g[i]->um1);
+    g[i]->step += steps[i];
+    sbfem_status st = finish_steps(g[i], s);
+    if (st != SBFEM_OK) return st;
+  }
+  return SBFEM_OK;
+}
+
 sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream) {
   if (n < 0 || (n > 0 && (!ms || !n_steps))) return fail(SBFEM_EINVAL, "bad batch arguments");
   hipStream_t s = (hipStream_t)hip_stream;
-  int64_t most = 0;
   for (int i = 0; i < n; ++i) {
     if (!ms[i] || n_steps[i] < 0) return fail(SBFEM_EINVAL, "bad batch entry %d", i);
+    for (int j = 0; j < i; ++j)
+      if (ms[j] == ms[i]) return fail(SBFEM_EINVAL, "mesh %d appears twice in the batch", i);
     sbfem_status st = check_flag(ms[i]);
     if (st != SBFEM_OK) return st;
-    most = std::max(most, n_steps[i]);
   }
+  // groups of owner-tile meshes with one library and one precision
+  std::vector<char> used(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (used[i] || ms[i]->assembly != SBFEM_ASM_TILED || ms[i]->profiling) continue;
+    std::vector<sbfem_mesh*> g;
+    std::vector<int64_t> st;
+    for (int j = i; j < n; ++j)
+      if (!used[j] && ms[j]->assembly == SBFEM_ASM_TILED && !ms[j]->profiling && ms[j]->P == ms[i]->P &&
+          ms[j]->prod == ms[i]->prod && ms[j]->walsh == ms[i]->walsh &&
+          ms[j]->block_threads == ms[i]->block_threads &&
+          ms[j]->block_threads_mixed == ms[i]->block_threads_mixed && n_steps[j] > 0) {
+        g.push_back(ms[j]);
+        st.push_back(n_steps[j]);
+        used[j] = 1;
+      }
+    if (!g.empty()) {
+      HIP_TRY(hipSetDevice(g[0]->device));
+      sbfem_status r = batch_tiled(g, st, s);
+      if (r != SBFEM_OK) return r;
+    }
+  }
+  // the rest, interleaved step by step
+  int64_t most = 0;
+  for (int i = 0; i < n; ++i)
+    if (!used[i]) most = std::max(most, n_steps[i]);
   for (int64_t k = 0; k < most; ++k)
     for (int i = 0; i < n; ++i)
-      if (k < n_steps[i]) {
+      if (!used[i] && k < n_steps[i]) {
         sbfem_status st = enqueue_step(ms[i], s);
         if (st != SBFEM_OK) return st;
       }
   for (int i = 0; i < n; ++i)
-    if (n_steps[i] > 0) {
+    if (!used[i] && n_steps[i] > 0) {
       sbfem_status st = finish_steps(ms[i], s);
       if (st != SBFEM_OK) return st;
     }

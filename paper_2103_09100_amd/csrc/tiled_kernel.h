@@ -155,7 +155,9 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
 // LDS holds the owned forces (FP64) and u of the local nodes: FP64 for FP64 products, and for
 // FP32 products u minus the displacement of the tile's first owned node, in FP32.
 template <bool PURE8, bool FP32, bool WALSH = false>
-__global__ void __launch_bounds__(512) tiled_step(TiledArgs a, int64_t first, int64_t count, int force_only) {
+__global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef* __restrict__ refs,
+                                                  const TileWork* __restrict__ work, int64_t first, int64_t count,
+                                                  int64_t k, int force_only) {
   using T = typename LdsType<FP32>::T;
   extern __shared__ double lds[];
   // XCD-contiguous block -> tile map
@@ -163,7 +165,17 @@ __global__ void __launch_bounds__(512) tiled_step(TiledArgs a, int64_t first, in
   const int64_t b = blockIdx.x;
   const int64_t t = (b % 8) * per + b / 8;
   if (t >= count) return;
-  const OwnerTile tile = a.tiles[first + t];
+  MeshRef r = single;
+  int64_t ti = first + t;
+  if (work) {
+    const TileWork w = work[first + t];
+    r = refs[w.mesh];
+    ti = w.tile;
+  }
+  // k steps after the step recorded in the mesh ref (batched calls advance every mesh together)
+  r.step += k;
+  const TiledArgs a = r.args[(r.parity + k) & 1];
+  const OwnerTile tile = a.tiles[ti];
   const int n_own = tile.n_own, n_local = tile.n_local;
   double* fl = lds;
   T* ul = (T*)(lds + 3 * (int64_t)n_own);
@@ -184,7 +196,7 @@ __global__ void __launch_bounds__(512) tiled_step(TiledArgs a, int64_t first, in
   if (!force_only)
     for (int i = tid; i < tile.n_load; i += nt) {
       const LoadEntry e = a.loads[tile.load0 + i];
-      atomicAdd(fl + e.ldof, -a.P * e.val);
+      atomicAdd(fl + e.ldof, -load_time(a.L, (double)r.step * a.dt) * e.val);
     }
   // the wave index is uniform in a wave: say so, so item fields (and K_p) come through scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;

@@ -22,13 +22,16 @@ def device_patterns(nu, stream=None, workers=0):
 
 
 class Simulation:
-    def __init__(self, mesh, dt=None, prod="fp64", state="fp64", assembly="atomic", orient_seed=None,
-                 u0=None, v0=None, stream=None, workers=0):
+    def __init__(self, mesh, dt=None, prod="fp64", state="fp64", assembly="tiled", orient_seed=None,
+                 u0=None, v0=None, stream=None, workers=0, tile_nodes=0, block_threads=0,
+                 block_threads_mixed=0):
         self.mesh = mesh
         self.patterns = device_patterns(mesh.nu, stream, workers)
         pid, code, conn = canonicalise(mesh, seed=orient_seed)
         desc, keep = binding.make_desc(mesh, pid, code, conn, dt=1.0, prod=prod, state=state,
-                                       assembly=assembly, u0=u0, v0=v0)
+                                       assembly=assembly, u0=u0, v0=v0, tile_nodes=tile_nodes,
+                                       block_threads=block_threads,
+                                       block_threads_mixed=block_threads_mixed)
         self.dt_cr = binding.critical_dt(self.patterns, desc)
         if dt is None:
             dt = mesh.load.get("dt_factor", 0.5) * self.dt_cr

@@ -192,3 +192,76 @@ def test_invalid_mesh_rejected(sim_mod):
     d, keep = binding.make_desc(m, p2, code, conn, dt=0.01)
     with pytest.raises(binding.SbfemError):
         binding.Mesh(pats, d, keep)
+
+
+def test_batched_meshes_match_alone_and_oracle(sim_mod):
+    """Uneven meshes advanced together (one launch per step) == each alone == the oracle."""
+    from paper_2103_09100_amd import binding
+    meshes = [configs.cfg1(), configs.small_zoo(), configs.cfg2(lcoarse=2, lfine=5, delta=0.1)]
+    steps = [120, 60, 90]
+    alone, batch = [], []
+    for m, n in zip(meshes, steps):
+        a = sim_mod.Simulation(m, prod="fp64", assembly="tiled")
+        a.step(n)
+        alone.append(a.u())
+        batch.append(sim_mod.Simulation(m, prod="fp64", assembly="tiled"))
+    binding.step_batch([b.gpu for b in batch], steps)
+    for m, n, a, b in zip(meshes, steps, alone, batch):
+        ub, nb = b.gpu.read(0)
+        assert nb == n
+        err = np.abs(ub - a).max() / np.abs(a).max()
+        _say(f"[batch vs alone {m.n_dof} dofs] {err:.3e}")
+        assert err <= 1e-12
+    o = Oracle(meshes[0])
+    ref = o.run(n_steps=steps[0], snap_every=0, energy=False)
+    err = np.abs(batch[0].u() - ref["u"]).max() / np.abs(ref["u"]).max()
+    assert err <= FP64_TOL
+    # a second batch call continues where the first stopped
+    binding.step_batch([b.gpu for b in batch[:2]], [10, 30])
+    assert batch[0].gpu.read(0)[1] == steps[0] + 10 and batch[1].gpu.read(0)[1] == steps[1] + 30
+
+
+@pytest.mark.parametrize("kind", ["triangle", "sine_burst", "damped"])
+def test_load_kinds_and_damping(sim_mod, kind):
+    m = configs.cfg1(n_steps=300)
+    if kind == "triangle":
+        m.load.update(kind="triangle", t1=0.3)
+    elif kind == "sine_burst":
+        m.load.update(kind="sine_burst", t1=1.0, cycles=5)
+    else:
+        m.load.update(alpha=0.8)
+    o = Oracle(m)
+    ref = o.run(n_steps=300)
+    for asm in ("tiled", "atomic"):
+        s = sim_mod.Simulation(m, assembly=asm)
+        e = relative_error(s.run(300, 50), ref["snapshots"])
+        _say(f"[{kind} {asm}] {e:.3e}")
+        assert e <= FP64_TOL
+
+
+def test_serving_results_equal_alone(sim_mod):
+    """Requests served in a mix (admission under a memory budget, batched steps) give the
+    same result as each request run alone."""
+    import torch
+    from paper_2103_09100_amd.serve import Request, Server, latency_stats
+    specs = [(1, 2e4, 80, 0.00), (2, 1.5e5, 140, 0.01), (3, 5e4, 60, 0.02), (4, 3e5, 100, 0.02),
+             (5, 1e4, 200, 0.05), (6, 8e4, 120, 0.06)]
+    reqs = [Request(rid, configs.request_mesh(rid, size, n), n, t) for rid, size, n, t in specs]
+    st, st2 = torch.cuda.Stream(), torch.cuda.Stream()
+    fps = []
+    for r in reqs:
+        s = sim_mod.Simulation(r.mesh, prod="fp64")
+        fps.append(s.footprint)
+        s.step(r.n_steps)
+        r.extra["alone"] = s.u()
+        s.close()
+    server = Server(budget_bytes=int(sum(fps) * 0.45), quantum=25, prod="fp64",
+                    stream=st.cuda_stream, setup_stream=st2.cuda_stream)
+    server.run(reqs)
+    for r in reqs:
+        err = np.abs(r.result - r.extra["alone"]).max() / np.abs(r.extra["alone"]).max()
+        _say(f"[serve rid {r.rid} {r.dofs} dofs] admitted {r.admitted:.3f}s finished {r.finished:.3f}s err {err:.2e}")
+        assert err <= 1e-12
+    stats = latency_stats(reqs)
+    _say(f"[serve] {stats}")
+    assert stats["n"] == len(reqs)

@@ -55,3 +55,17 @@ def test_argument_validation_without_device(binding):
     assert st == binding.EINVAL
     st = lib.sbfem_read_state(None, 0, None, None, None)
     assert st == binding.EINVAL
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the binding (before or after torch) maps exactly one HIP runtime."""
+    import subprocess
+    import sys
+    code = ("import {first}\nimport {second}\n"
+            "paths = set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)\n"
+            "print(len(paths))\n")
+    for first, second in (("paper_2103_09100_amd.binding", "torch"), ("torch", "paper_2103_09100_amd.binding")):
+        out = subprocess.run([sys.executable, "-c", code.format(first=first, second=second)], cwd=ROOT,
+                             capture_output=True, text=True, timeout=300)
+        assert out.returncode == 0, out.stderr
+        assert out.stdout.split()[-1] == "1", (first, second, out.stdout)
