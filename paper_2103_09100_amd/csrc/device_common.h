@@ -8,6 +8,53 @@
 
 namespace sbfem {
 
+// Address-space views.  Pointers that arrive through a struct in device memory are
+// generic (flat) pointers to the compiler; a flat load waits on both the vector and
+// the LDS counters and may alias LDS.  Data that no kernel writes during the launch
+// (tables, layouts, master matrices) is read through the constant space (scalar
+// loads when the address is uniform), other device arrays through the global space.
+template <class T>
+using cptr_t = const __attribute__((address_space(4))) T*;
+template <class T>
+using gptr_t = const __attribute__((address_space(1))) T*;
+template <class T>
+using gmut_t = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ cptr_t<T> as_const(const T* p) {
+  return (cptr_t<T>)p;
+}
+template <class T>
+__device__ __forceinline__ gptr_t<T> as_global(const T* p) {
+  return (gptr_t<T>)p;
+}
+template <class T>
+__device__ __forceinline__ gmut_t<T> as_global_mut(T* p) {
+  return (gmut_t<T>)p;
+}
+
+// Copy of a struct read through such a view, dword by dword (the compiler merges the loads).
+template <class T>
+__device__ __forceinline__ T load_const(cptr_t<T> p) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+  T v;
+  const cptr_t<uint32_t> q = (cptr_t<uint32_t>)p;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+  return v;
+}
+template <class T>
+__device__ __forceinline__ T load_global(gptr_t<T> p) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+  T v;
+  const gptr_t<uint32_t> q = (gptr_t<uint32_t>)p;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+  return v;
+}
+
 // orientation code -> axis permutation pi and signs s:  u_master[k][a] = s_a u[node][pi(a)]
 __device__ __forceinline__ void decode_orient(int code, int& p0, int& p1, int& p2,
                                               double& s0, double& s1, double& s2) {

@@ -33,10 +33,13 @@ struct OwnerTile {
 };
 
 // Up to one wave of cells of one pattern; rows (master slots) in mask are accumulated.
+// Generic tiles: node indices slot-major, lidx[lidx0 + k*count + lane], per-cell
+// orientation/level/material at cell0, koff = master matrix offset.  Pure 8-node
+// tiles: indices lane-major, lidx[lidx0 + 8*lane + k], koff = 72 * scale class.
 struct CellItem {
-  int64_t lidx0;   // local node indices, slot-major: lidx[lidx0 + k*count + lane]
-  int64_t cell0;   // per-cell orientation/level/material
-  int64_t koff;    // master matrix offset
+  int64_t lidx0;
+  int64_t cell0;
+  int64_t koff;
   int32_t nn;
   int32_t count;
   uint32_t mask;
@@ -66,6 +69,8 @@ struct TiledArgs {
   const double* W64;    // 8-node master matrix as 8 blocks of 3x3 in the corner Walsh basis (or null)
   const float* W32;
   int64_t walsh_koff;   // master-matrix offset of the 8-node pattern (-1: none)
+  const double* Ws64;   // the same blocks times s_e of each scale class (72 per class), pure 8-node tiles
+  const float* Ws32;
   const double* u;      // u_n
   double* um1;          // u_{n-1} in, u_{n+1} out (owned nodes)
   const double* minv;
@@ -146,7 +151,6 @@ struct TiledLaunch {
   int64_t n_pure8 = 0, n_mixed = 0;
   int64_t k = 0;                       // batch: steps since the refs were recorded
   bool fp32 = false;
-  bool walsh = false;
   bool force_only = false;
   int32_t threads8 = 512, threads_mixed = 256;
   size_t lds = 0;

@@ -143,22 +143,21 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 #undef SBFEM_L
 }
 
-// 8-node owner tiles
+// pure 8-node owner tiles
 void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
-#define SBFEM_L(F, W)                                                                                         \
-  do {                                                                                                        \
-    if (L.lds > 65536)                                                                                        \
-      (void)hipFuncSetAttribute((const void*)tiled_step<true, F, W>,                                          \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds);                      \
-    hipLaunchKernelGGL((tiled_step<true, F, W>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, \
-                       L.refs, work, first, count, L.k, (int)L.force_only);                                        \
+#define SBFEM_L(F)                                                                                              \
+  do {                                                                                                          \
+    if (L.lds > 65536)                                                                                          \
+      (void)hipFuncSetAttribute((const void*)tiled_step8<F>, hipFuncAttributeMaxDynamicSharedMemorySize,         \
+                                (int)L.lds);                                                                    \
+    hipLaunchKernelGGL((tiled_step8<F>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, L.refs,    \
+                       work, first, count, L.k, (int)L.force_only);                                             \
   } while (0)
-  if (L.fp32) {
-    if (L.walsh) SBFEM_L(true, true); else SBFEM_L(true, false);
-  } else {
-    if (L.walsh) SBFEM_L(false, true); else SBFEM_L(false, false);
-  }
+  if (L.fp32)
+    SBFEM_L(true);
+  else
+    SBFEM_L(false);
 #undef SBFEM_L
 }
 

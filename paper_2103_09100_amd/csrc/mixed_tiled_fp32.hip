@@ -7,9 +7,9 @@ void tiled_mixed_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t
                              hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
   if (L.lds > 65536)
-    (void)hipFuncSetAttribute((const void*)tiled_step<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)tiled_step<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)L.lds);
-  hipLaunchKernelGGL((tiled_step<false, true>), dim3((unsigned)blocks), dim3(L.threads_mixed), L.lds, s, L.single,
+  hipLaunchKernelGGL((tiled_step<true>), dim3((unsigned)blocks), dim3(L.threads_mixed), L.lds, s, L.single,
                      L.refs, work, first, count, L.k, (int)L.force_only);
 }
 

@@ -69,6 +69,18 @@ void decode(int code, int pi[3], double s[3]) {
   for (int a = 0; a < 3; ++a) s[a] = ((code >> a) & 1) ? -1.0 : 1.0;
 }
 
+// corner k = i + 2j + 4l of the master (at (2i-1, 2j-1, 2l-1)) is corner corner_image(k) of a cell
+// in orientation (pi, s): the cell position q has q[pi(a)] = s_a p[a]
+int corner_image(int k, const int pi[3], const double s[3]) {
+  int n = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int pa = ((k >> a) & 1) ? 1 : -1;
+    const int q = s[a] > 0 ? pa : -pa;
+    if (q > 0) n |= 1 << pi[a];
+  }
+  return n;
+}
+
 double load_time_host(const sbfem::LoadParams& L, double t) {
   if (L.kind == SBFEM_LOAD_RICKER) {
     const double tau = (t - L.t1) / (L.t1 / 5.0);
@@ -98,6 +110,10 @@ struct sbfem_patterns {
   int64_t walsh_koff = -1;
   double* dW64 = nullptr;
   float* dW32 = nullptr;
+  std::vector<double> W;  // host copy of the Walsh blocks (72)
+  // the 8-node pattern when its matrix is also invariant under the 48 cube transformations:
+  // its cells are then mapped onto it in identity orientation and run the pure 8-node kernel
+  int32_t p8 = -1;
 };
 
 struct sbfem_mesh {
@@ -144,6 +160,8 @@ struct sbfem_mesh {
   int64_t n_pure8 = 0, n_mixed = 0;
   int32_t lds_bytes = 0;
   sbfem::TiledArgs* d_args = nullptr;   // two argument blocks: (u=buf0, prev=buf1) and swapped
+  double* dWs64 = nullptr;              // Walsh blocks times s_e per scale class (pure 8-node tiles)
+  float* dWs32 = nullptr;
   double* buf0 = nullptr;
   int32_t block_threads = 512;        // 8-node owner tiles
   int32_t block_threads_mixed = 256;  // owner tiles with larger cells
@@ -267,8 +285,26 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
               off = std::max(off, std::fabs(v));
           }
     if (off <= 1e-12 * kmax / 8.0) p->walsh_koff = p->koff[pid];
+    // invariance under every transformation g:  K[3k+a][3k'+a'] = s_a s_a' K[3n(k)+pi(a)][3n(k')+pi(a')],
+    // where corner k of the master sits at corner n(k) of the cell (Sec. 3.2.2)
+    double dev = 0.0;
+    for (int code = 0; code < 48; ++code) {
+      int pi[3], nk[8];
+      double sg[3];
+      decode(code, pi, sg);
+      for (int k = 0; k < 8; ++k) nk[k] = corner_image(k, pi, sg);
+      for (int k = 0; k < 8; ++k)
+        for (int a = 0; a < 3; ++a)
+          for (int k2 = 0; k2 < 8; ++k2)
+            for (int a2 = 0; a2 < 3; ++a2) {
+              const double v = sg[a] * sg[a2] * Kp[(3 * nk[k] + pi[a]) * 24 + 3 * nk[k2] + pi[a2]];
+              dev = std::max(dev, std::fabs(v - Kp[(3 * k + a) * 24 + 3 * k2 + a2]));
+            }
+    }
+    if (p->walsh_koff >= 0 && dev <= 1e-12 * kmax) p->p8 = pid;
     break;
   }
+  p->W = W;
   std::vector<float> W32(W.begin(), W.end());
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t e = hipGetDevice(&p->device);
@@ -356,6 +392,8 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->nodelist);
   dfree(m->tloads);
   dfree(m->d_args);
+  dfree(m->dWs64);
+  dfree(m->dWs32);
   delete m;
 }
 
@@ -414,6 +452,8 @@ static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const double* u, dou
   a.W64 = m->P->dW64;
   a.W32 = m->P->dW32;
   a.walsh_koff = m->walsh ? m->P->walsh_koff : -1;
+  a.Ws64 = m->dWs64;
+  a.Ws32 = m->dWs32;
   a.u = u;
   a.um1 = um1;
   a.minv = m->minv;
@@ -438,7 +478,6 @@ static sbfem::TiledLaunch tiled_launch(const sbfem_mesh* m, bool force_only) {
   L.n_pure8 = m->n_pure8;
   L.n_mixed = m->n_mixed;
   L.fp32 = m->prod == SBFEM_PROD_FP32;
-  L.walsh = m->walsh && m->P->walsh_koff >= 0;
   L.force_only = force_only;
   L.threads8 = m->block_threads;
   L.threads_mixed = m->block_threads_mixed;
@@ -494,6 +533,21 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   }
   std::vector<int32_t> iconn(total);
   for (int64_t i = 0; i < total; ++i) iconn[i] = ext2int[d->conn[i]];
+  // Cells of the 8-node pattern, whose matrix (and lumped mass) is invariant under the
+  // 48 cube transformations, are re-listed in identity orientation: the master matrix
+  // applies to the cell's own corner order and no transformation is needed per step.
+  std::vector<uint8_t> orient(d->orient, d->orient + C);
+  if (p->p8 >= 0) {
+    for (int64_t c = 0; c < C; ++c) {
+      if (d->pattern[c] != p->p8 || orient[c] == 0) continue;
+      int pi[3], nat[8];
+      double sg[3];
+      decode(orient[c], pi, sg);
+      for (int k = 0; k < 8; ++k) nat[corner_image(k, pi, sg)] = iconn[cptr[c] + k];
+      for (int k = 0; k < 8; ++k) iconn[cptr[c] + k] = nat[k];
+      orient[c] = 0;
+    }
+  }
 
   auto* m = new sbfem_mesh();
   m->P = p;
@@ -520,7 +574,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     const double sc = d->rho[d->material[c]] * h * h * h;
     int pi[3];
     double sg[3];
-    decode(d->orient[c], pi, sg);
+    decode(orient[c], pi, sg);
     const double* mp = p->m.data() + p->moff[pid];
     for (int64_t k = 0; k < cptr[c + 1] - cptr[c]; ++k)
       for (int a = 0; a < 3; ++a) mdiag[3 * (int64_t)iconn[cptr[c] + k] + pi[a]] += sc * mp[3 * k + a];
@@ -585,7 +639,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     ti.cptr = cptr.data();
     ti.conn = iconn.data();
     ti.pattern = d->pattern;
-    ti.orient = d->orient;
+    ti.orient = orient.data();
     ti.level = d->level;
     ti.material = d->material;
     ti.pattern_ndof = p->ndof.data();
@@ -616,11 +670,14 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     threads_desc(d->block_threads_mixed, m->block_threads_mixed);
     if (d->tile_nodes > 0) tn0 = std::max(32, d->tile_nodes);
     if (const char* ev = std::getenv("SBFEM_DENSE8")) m->walsh = std::atoi(ev) == 0;
+    ti.p8 = m->walsh ? p->p8 : -1;
     bool ok = false;
+    // LDS per block: FP64 forces of the owned nodes, u of the local nodes (FP64: 24 B per node;
+    // FP32: 12 B, 16 B in pure 8-node tiles)
+    const int64_t node_bytes = d->prod == SBFEM_PROD_FP32 ? 16 : 24;
     for (int32_t tn = tn0; tn >= 32; tn /= 2) {
-      const int64_t vbytes = d->prod == SBFEM_PROD_FP32 ? 4 : 8;
-      if (sbfem::build_owner_tiles(ti, tn, to) && 3 * vbytes * to.max_local + 24 * to.tile_nodes <= lds_max) {
-        m->lds_bytes = (int32_t)(3 * vbytes * to.max_local + 24 * to.tile_nodes);
+      if (sbfem::build_owner_tiles(ti, tn, to) && node_bytes * to.max_local + 24 * to.tile_nodes <= lds_max) {
+        m->lds_bytes = (int32_t)(node_bytes * to.max_local + 24 * to.tile_nodes);
         ok = true;
         break;
       }
@@ -635,7 +692,9 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     m->layout[1] = to.n_mixed;
     m->layout[2] = (int64_t)to.items.size();
     m->layout[3] = (int64_t)to.nodelist.size() + N;
-    m->layout[4] = (int64_t)to.orient.size();
+    m->layout[4] = (int64_t)to.orient.size();  // cell entries of generic tiles
+    for (int64_t t = 0; t < to.n_pure8; ++t)       // plus those of pure 8-node tiles
+      for (int32_t w = 0; w < to.tiles[t].n_items; ++w) m->layout[4] += to.items[to.tiles[t].item0 + w].count;
     m->layout[5] = to.tile_nodes;
     ALLOC(otiles, to.tiles.size())
     ALLOC(items, to.items.size())
@@ -646,6 +705,22 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     ALLOC(level, to.level.size())
     ALLOC(material, to.material.size())
     ALLOC(d_args, 2)
+    // Walsh blocks pre-multiplied by s_e = E h of each scale class (one rounding per entry)
+    const size_t ncls = to.scale_keys.size();
+    std::vector<double> ws64(std::max<size_t>(1, ncls) * 72, 0.0);
+    std::vector<float> ws32(ws64.size(), 0.0f);
+    for (size_t c = 0; c < ncls; ++c) {
+      const int lev = to.scale_keys[c] >> 8, mat = to.scale_keys[c] & 255;
+      const double se = d->E[mat] * std::ldexp(d->h0, -lev);
+      for (int i = 0; i < 72; ++i) {
+        ws64[72 * c + i] = se * p->W[i];
+        ws32[72 * c + i] = (float)ws64[72 * c + i];
+      }
+    }
+    ALLOC(dWs64, ws64.size())
+    ALLOC(dWs32, ws32.size())
+    H2D(m->dWs64, ws64.data(), ws64.size() * 8);
+    H2D(m->dWs32, ws32.data(), ws32.size() * 4);
     H2D(m->otiles, to.tiles.data(), to.tiles.size() * sizeof(sbfem::OwnerTile));
     H2D(m->items, to.items.data(), to.items.size() * sizeof(sbfem::CellItem));
     H2D(m->lidx, to.lidx.data(), to.lidx.size() * 2);
@@ -707,7 +782,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
       for (int64_t j = 0; j < cnt; ++j) {
         const int64_t c = order[i0 + j];
         for (int k = 0; k < nn; ++k) sconn[cpos + (int64_t)k * cnt + j] = iconn[cptr[c] + k];
-        sorient[i0 + j] = d->orient[c];
+        sorient[i0 + j] = orient[c];
         slevel[i0 + j] = d->level[c];
         smat[i0 + j] = d->material[c];
       }
@@ -955,7 +1030,7 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
     std::vector<int64_t> st;
     for (int j = i; j < n; ++j)
       if (!used[j] && ms[j]->assembly == SBFEM_ASM_TILED && !ms[j]->profiling && ms[j]->P == ms[i]->P &&
-          ms[j]->prod == ms[i]->prod && ms[j]->walsh == ms[i]->walsh &&
+          ms[j]->prod == ms[i]->prod &&
           ms[j]->block_threads == ms[i]->block_threads &&
           ms[j]->block_threads_mixed == ms[i]->block_threads_mixed && n_steps[j] > 0) {
         g.push_back(ms[j]);

@@ -6,6 +6,12 @@
 // such cell only the rows of owned nodes are accumulated.  Cells are grouped
 // into wave-sized items of one pattern and one row mask so that the master
 // matrix and the row selection are uniform within a wave.
+//
+// Tiles whose cells are all regular 8-node cells (pattern p8, identity
+// orientation) are laid out for the dedicated kernel: items of one scale class
+// (level, material) so the pre-scaled Walsh blocks are uniform in a wave, full
+// waves (cells sorted by row mask, the item's mask is the union), and the eight
+// local node indices of a cell stored together (16 bytes, lane-major).
 #include <algorithm>
 #include <thread>
 #include <unordered_map>
@@ -52,6 +58,22 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
     for (int64_t c = 0; c < C; ++c)
       for (int64_t i = in.cptr[c]; i < in.cptr[c + 1]; ++i) ncell[pos[in.conn[i]]++] = (int32_t)c;
   }
+  // scale class of every 8-node cell: (level, material) in order of first use
+  std::vector<int32_t> cls(in.p8 >= 0 ? C : 0, -1);
+  out = TilingOutput();
+  if (in.p8 >= 0) {
+    std::unordered_map<int32_t, int32_t> seen;
+    for (int64_t c = 0; c < C; ++c) {
+      if (in.pattern[c] != in.p8) continue;
+      const int32_t key = (int32_t)in.level[c] * 256 + in.material[c];
+      auto it = seen.find(key);
+      if (it == seen.end()) {
+        it = seen.emplace(key, (int32_t)out.scale_keys.size()).first;
+        out.scale_keys.push_back(key);
+      }
+      cls[c] = it->second;
+    }
+  }
   // load entries by node
   std::unordered_map<int64_t, double> bmap;
   for (size_t i = 0; i < in.load_dof.size(); ++i) bmap[in.load_dof[i]] += in.load_val[i];
@@ -95,58 +117,84 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
         li_flat.push_back((uint16_t)l);
       }
       li_off[j + 1] = (int64_t)li_flat.size();
-      if (in.pattern_ndof[in.pattern[c]] != 24) r.pure8 = false;
+      if (in.p8 < 0 || in.pattern[c] != in.p8) r.pure8 = false;
       recs.push_back({(int32_t)j, mask, (int32_t)in.pattern[c]});
     }
-    // group by (pattern, row mask); small groups of one pattern share an item with the union mask
-    std::sort(recs.begin(), recs.end(), [](const CellRec& a, const CellRec& b) {
-      return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
-    });
-    const size_t kMerge = 16;
-    size_t i0 = 0;
-    std::vector<std::vector<CellRec>> groups;
-    std::vector<CellRec> small;
-    int32_t small_pat = -1;
-    auto flush_small = [&] {
-      if (!small.empty()) groups.push_back(small);
-      small.clear();
-    };
-    while (i0 < recs.size()) {
-      size_t i1 = i0;
-      while (i1 < recs.size() && recs[i1].pattern == recs[i0].pattern && recs[i1].mask == recs[i0].mask) ++i1;
-      std::vector<CellRec> g(recs.begin() + i0, recs.begin() + i1);
-      if (g.size() < kMerge) {
-        if (small_pat != g[0].pattern) flush_small();
-        small_pat = g[0].pattern;
-        small.insert(small.end(), g.begin(), g.end());
-      } else {
-        groups.push_back(g);
-      }
-      i0 = i1;
-    }
-    flush_small();
-    for (auto& g : groups) {
-      for (size_t a = 0; a < g.size(); a += kWave) {
-        const size_t cnt = std::min<size_t>(kWave, g.size() - a);
+    if (r.pure8) {
+      // one scale class per item, cells sorted by row mask, full waves with the union mask
+      for (auto& rc : recs) rc.pattern = cls[cells[rc.c]];
+      std::sort(recs.begin(), recs.end(), [](const CellRec& a, const CellRec& b) {
+        return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
+      });
+      size_t i0 = 0;
+      while (i0 < recs.size()) {
+        size_t i1 = i0;
+        while (i1 < recs.size() && i1 - i0 < (size_t)kWave && recs[i1].pattern == recs[i0].pattern) ++i1;
         CellItem it{};
-        const int32_t pid = g[a].pattern;
-        const int nn = in.pattern_ndof[pid] / 3;
         it.lidx0 = (int64_t)r.lidx.size();
-        it.cell0 = (int64_t)r.orient.size();
-        it.koff = in.pattern_koff[pid];
-        it.nn = nn;
-        it.count = (int32_t)cnt;
+        it.cell0 = 0;
+        it.koff = 72 * (int64_t)recs[i0].pattern;
+        it.nn = 8;
+        it.count = (int32_t)(i1 - i0);
         it.mask = 0;
-        for (size_t b = 0; b < cnt; ++b) it.mask |= g[a + b].mask;
-        for (int k = 0; k < nn; ++k)
-          for (size_t b = 0; b < cnt; ++b) r.lidx.push_back(li_flat[li_off[g[a + b].c] + k]);
-        for (size_t b = 0; b < cnt; ++b) {
-          const int32_t c = cells[g[a + b].c];
-          r.orient.push_back(in.orient[c]);
-          r.level.push_back(in.level[c]);
-          r.material.push_back(in.material[c]);
+        for (size_t b = i0; b < i1; ++b) {
+          it.mask |= recs[b].mask;
+          for (int k = 0; k < 8; ++k) r.lidx.push_back(li_flat[li_off[recs[b].c] + k]);
         }
         r.items.push_back(it);
+        i0 = i1;
+      }
+    } else {
+      // group by (pattern, row mask); small groups of one pattern share an item with the union mask
+      std::sort(recs.begin(), recs.end(), [](const CellRec& a, const CellRec& b) {
+        return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
+      });
+      const size_t kMerge = 16;
+      size_t i0 = 0;
+      std::vector<std::vector<CellRec>> groups;
+      std::vector<CellRec> small;
+      int32_t small_pat = -1;
+      auto flush_small = [&] {
+        if (!small.empty()) groups.push_back(small);
+        small.clear();
+      };
+      while (i0 < recs.size()) {
+        size_t i1 = i0;
+        while (i1 < recs.size() && recs[i1].pattern == recs[i0].pattern && recs[i1].mask == recs[i0].mask) ++i1;
+        std::vector<CellRec> g(recs.begin() + i0, recs.begin() + i1);
+        if (g.size() < kMerge) {
+          if (small_pat != g[0].pattern) flush_small();
+          small_pat = g[0].pattern;
+          small.insert(small.end(), g.begin(), g.end());
+        } else {
+          groups.push_back(g);
+        }
+        i0 = i1;
+      }
+      flush_small();
+      for (auto& g : groups) {
+        for (size_t a = 0; a < g.size(); a += kWave) {
+          const size_t cnt = std::min<size_t>(kWave, g.size() - a);
+          CellItem it{};
+          const int32_t pid = g[a].pattern;
+          const int nn = in.pattern_ndof[pid] / 3;
+          it.lidx0 = (int64_t)r.lidx.size();
+          it.cell0 = (int64_t)r.orient.size();
+          it.koff = in.pattern_koff[pid];
+          it.nn = nn;
+          it.count = (int32_t)cnt;
+          it.mask = 0;
+          for (size_t b = 0; b < cnt; ++b) it.mask |= g[a + b].mask;
+          for (int k = 0; k < nn; ++k)
+            for (size_t b = 0; b < cnt; ++b) r.lidx.push_back(li_flat[li_off[g[a + b].c] + k]);
+          for (size_t b = 0; b < cnt; ++b) {
+            const int32_t c = cells[g[a + b].c];
+            r.orient.push_back(in.orient[c]);
+            r.level.push_back(in.level[c]);
+            r.material.push_back(in.material[c]);
+          }
+          r.items.push_back(it);
+        }
       }
     }
     for (int64_t n = own0; n < own1; ++n)
@@ -157,7 +205,6 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
   });
 
   // concatenate: pure 8-node tiles first, then the others
-  out = TilingOutput();
   out.tile_nodes = tile_nodes;
   for (int pass = 0; pass < 2; ++pass) {
     for (int64_t t = 0; t < n_tiles; ++t) {

@@ -19,6 +19,8 @@ struct TilingInput {
   const uint8_t* material = nullptr;
   const int32_t* pattern_ndof = nullptr;
   const int64_t* pattern_koff = nullptr;
+  // 8-node cells of this pattern (identity orientation) form the pure 8-node tiles; -1: none
+  int32_t p8 = -1;
   std::vector<int64_t> load_dof;       // internal dofs
   std::vector<double> load_val;
 };
@@ -33,6 +35,9 @@ struct TilingOutput {
   std::vector<uint16_t> lidx;
   std::vector<uint8_t> orient, level, material;
   std::vector<LoadEntry> loads;
+  // scale classes of the pure 8-node tiles: key = level * 256 + material, in order of first use;
+  // an item of such a tile carries koff = 72 * class
+  std::vector<int32_t> scale_keys;
 };
 
 // false if a tile would need more than 65535 local nodes
