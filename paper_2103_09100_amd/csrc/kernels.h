@@ -33,9 +33,10 @@ struct OwnerTile {
 };
 
 // Up to one wave of cells of one pattern; rows (master slots) in mask are accumulated.
-// Generic tiles: node indices slot-major, lidx[lidx0 + k*count + lane], per-cell
-// orientation/level/material at cell0, koff = master matrix offset.  Pure 8-node
-// tiles: indices lane-major, lidx[lidx0 + 8*lane + k], koff = 72 * scale class.
+// kind 0 (any pattern): node indices slot-major, lidx[lidx0 + k*count + lane], per-cell
+// orientation/level/material at cell0, koff = master matrix offset.
+// kind 1 (regular 8-node cells of one scale class, identity orientation): indices
+// lane-major, lidx[lidx0 + 8*lane + k] (lidx0 a multiple of 8), koff = kWalshC * class.
 struct CellItem {
   int64_t lidx0;
   int64_t cell0;
@@ -43,8 +44,11 @@ struct CellItem {
   int32_t nn;
   int32_t count;
   uint32_t mask;
-  int32_t pad;
+  int32_t kind;
 };
+
+// Entries per scale class of the structured Walsh table of the 8-node cell (31 used).
+constexpr int kWalshC = 32;
 
 struct LoadEntry {
   int32_t ldof;    // 3 * local owned node + axis
@@ -66,10 +70,7 @@ struct TiledArgs {
   double h0;
   const double* K64;
   const float* K32;
-  const double* W64;    // 8-node master matrix as 8 blocks of 3x3 in the corner Walsh basis (or null)
-  const float* W32;
-  int64_t walsh_koff;   // master-matrix offset of the 8-node pattern (-1: none)
-  const double* Ws64;   // the same blocks times s_e of each scale class (72 per class), pure 8-node tiles
+  const double* Ws64;   // 8-node cell: structured Walsh table times s_e, kWalshC per scale class
   const float* Ws32;
   const double* u;      // u_n
   double* um1;          // u_{n-1} in, u_{n+1} out (owned nodes)

@@ -108,12 +108,11 @@ struct sbfem_patterns {
   float* dK32 = nullptr;
   // 8-node pattern in the corner Walsh basis (8 blocks of 3x3), if its matrix has that structure
   int64_t walsh_koff = -1;
-  double* dW64 = nullptr;
-  float* dW32 = nullptr;
-  std::vector<double> W;  // host copy of the Walsh blocks (72)
   // the 8-node pattern when its matrix is also invariant under the 48 cube transformations:
-  // its cells are then mapped onto it in identity orientation and run the pure 8-node kernel
+  // its cells are then mapped onto it in identity orientation and take the Walsh path with
+  // the structured table Wc (sbfem::kWalshC entries, layout as in the device code)
   int32_t p8 = -1;
+  std::vector<double> Wc;
 };
 
 struct sbfem_mesh {
@@ -301,27 +300,52 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
               dev = std::max(dev, std::fabs(v - Kp[(3 * k + a) * 24 + 3 * k2 + a2]));
             }
     }
-    if (p->walsh_koff >= 0 && dev <= 1e-12 * kmax) p->p8 = pid;
+    // structured table: translation modes carry no force, block 1 << m couples only the axes
+    // other than m, block 7 ^ (1 << m) keeps axis m on its own, blocks 0 and 7 are (d - o) I + o J
+    auto Wb = [&](int t, int a2, int a) { return W[t * 9 + a2 * 3 + a]; };
+    double wmax = 0.0, werr = 0.0;
+    for (double v : W) wmax = std::max(wmax, std::fabs(v));
+    for (int t = 0; t < 8; ++t)
+      for (int a2 = 0; a2 < 3; ++a2)
+        for (int a = 0; a < 3; ++a) {
+          bool zero = (t == (1 << a2)) || (t == (1 << a));
+          if (t == 3 || t == 5 || t == 6) {
+            const int m = t == 3 ? 2 : (t == 5 ? 1 : 0);
+            zero = zero || ((a2 == m) != (a == m));
+          }
+          if (zero) werr = std::max(werr, std::fabs(Wb(t, a2, a)));
+          if (t == 0 || t == 7)
+            werr = std::max(werr, std::fabs(Wb(t, a2, a) - (a2 == a ? Wb(t, 0, 0) : Wb(t, 0, 1))));
+        }
+    std::vector<double> Wc(sbfem::kWalshC, 0.0);
+    Wc[0] = Wb(0, 0, 0) - Wb(0, 0, 1);
+    Wc[1] = Wb(0, 0, 1);
+    Wc[2] = Wb(7, 0, 0) - Wb(7, 0, 1);
+    Wc[3] = Wb(7, 0, 1);
+    for (int mm = 0; mm < 3; ++mm) {
+      const int i = mm == 0 ? 1 : 0, j = mm == 2 ? 1 : 2;
+      const int t1 = 1 << mm, t2 = 7 ^ (1 << mm);
+      const double b1[4] = {Wb(t1, i, i), Wb(t1, i, j), Wb(t1, j, i), Wb(t1, j, j)};
+      const double b2[5] = {Wb(t2, i, i), Wb(t2, i, j), Wb(t2, j, i), Wb(t2, j, j), Wb(t2, mm, mm)};
+      for (int q = 0; q < 4; ++q) Wc[4 + 4 * mm + q] = b1[q];
+      for (int q = 0; q < 5; ++q) Wc[16 + 5 * mm + q] = b2[q];
+    }
+    if (p->walsh_koff >= 0 && dev <= 1e-12 * kmax && werr <= 1e-12 * wmax) {
+      p->p8 = pid;
+      p->Wc = Wc;
+    }
     break;
   }
-  p->W = W;
-  std::vector<float> W32(W.begin(), W.end());
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = dalloc(&p->dK64, ko);
   if (e == hipSuccess) e = dalloc(&p->dK32, ko);
   if (e == hipSuccess) e = hipMemcpyAsync(p->dK64, p->K.data(), ko * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(p->dK32, K32.data(), ko * 4, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = dalloc(&p->dW64, 72);
-  if (e == hipSuccess) e = dalloc(&p->dW32, 72);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->dW64, W.data(), 72 * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->dW32, W32.data(), 72 * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     dfree(p->dK64);
     dfree(p->dK32);
-    dfree(p->dW64);
-    dfree(p->dW32);
     delete p;
     return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "pattern upload: %s", hipGetErrorString(e));
   }
@@ -334,8 +358,6 @@ void sbfem_destroy_patterns(sbfem_patterns* p) {
   (void)hipSetDevice(p->device);
   dfree(p->dK64);
   dfree(p->dK32);
-  dfree(p->dW64);
-  dfree(p->dW32);
   delete p;
 }
 
@@ -449,9 +471,6 @@ static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const double* u, dou
   a.h0 = m->h0;
   a.K64 = m->P->dK64;
   a.K32 = m->P->dK32;
-  a.W64 = m->P->dW64;
-  a.W32 = m->P->dW32;
-  a.walsh_koff = m->walsh ? m->P->walsh_koff : -1;
   a.Ws64 = m->dWs64;
   a.Ws32 = m->dWs32;
   a.u = u;
@@ -705,16 +724,17 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     ALLOC(level, to.level.size())
     ALLOC(material, to.material.size())
     ALLOC(d_args, 2)
-    // Walsh blocks pre-multiplied by s_e = E h of each scale class (one rounding per entry)
+    // structured Walsh table pre-multiplied by s_e = E h of each scale class (one rounding per entry)
     const size_t ncls = to.scale_keys.size();
-    std::vector<double> ws64(std::max<size_t>(1, ncls) * 72, 0.0);
+    const int WC = sbfem::kWalshC;
+    std::vector<double> ws64(std::max<size_t>(1, ncls) * WC, 0.0);
     std::vector<float> ws32(ws64.size(), 0.0f);
     for (size_t c = 0; c < ncls; ++c) {
       const int lev = to.scale_keys[c] >> 8, mat = to.scale_keys[c] & 255;
       const double se = d->E[mat] * std::ldexp(d->h0, -lev);
-      for (int i = 0; i < 72; ++i) {
-        ws64[72 * c + i] = se * p->W[i];
-        ws32[72 * c + i] = (float)ws64[72 * c + i];
+      for (int i = 0; i < WC; ++i) {
+        ws64[WC * c + i] = se * p->Wc[i];
+        ws32[WC * c + i] = (float)ws64[WC * c + i];
       }
     }
     ALLOC(dWs64, ws64.size())

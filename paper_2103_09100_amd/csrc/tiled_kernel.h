@@ -34,13 +34,22 @@ __device__ __forceinline__ T pick3t(int i, T x, T y, T z) {
 // The regular 8-node cell is symmetric under the three mirror planes, so in the
 // basis of Walsh functions over its corners (per displacement component) its
 // master matrix splits into 8 blocks of 3x3: mode (a, s) of component a and
-// corner character s couples only to modes of the same parity type s ^ (1 << a).
-// f = K u becomes: forward butterflies (24 adds per component), 72 products,
-// inverse butterflies.  Corner k = i + 2j + 4l sits at (2i-1, 2j-1, 2l-1);
-// W holds the blocks with the 1/64 normalisation (and, for pure 8-node tiles,
-// the cell scale) folded in.
+// corner character s couples only to modes of the same type t = s ^ (1 << a).
+// Corner k = i + 2j + 4l sits at (2i-1, 2j-1, 2l-1).  The full cube symmetry
+// fixes more: the translation modes (s = 0) carry no force, block t = 1 << m
+// couples only the two axes other than m, block t = 7 ^ (1 << m) couples the two
+// axes of t and keeps axis m on its own, and blocks 0 and 7 have the form
+// (d - o) I + o J.  The table C holds the 31 remaining coefficients (with the
+// 1/64 normalisation and the cell scale s_e folded in):
+//   [0] d0 - o0, [1] o0, [2] d7 - o7, [3] o7,
+//   [4 + 4m]  t = 1 << m:       B_ii, B_ij, B_ji, B_jj over the axes i < j other than m,
+//   [16 + 5m] t = 7 ^ (1 << m): B_ii, B_ij, B_ji, B_jj, B_mm.
+// f = K u: forward butterflies, 39 products, inverse butterflies (174 operations).
+__device__ __forceinline__ constexpr int other_lo(int m) { return m == 0 ? 1 : 0; }
+__device__ __forceinline__ constexpr int other_hi(int m) { return m == 2 ? 1 : 2; }
+
 template <typename T>
-__device__ __forceinline__ void walsh8_apply(cptr_t<T> W, const T (&ue)[24], T (&fe)[24]) {
+__device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&fe)[24]) {
   T x[3][8];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -54,19 +63,41 @@ __device__ __forceinline__ void walsh8_apply(cptr_t<T> W, const T (&ue)[24], T (
       for (int k = 0; k < 8; ++k)
         if (!((k >> b) & 1)) {
           const T lo = x[a][k], hi = x[a][k | (1 << b)];
-          x[a][k] = lo + hi;
+          if (b < 2 || k != 0) x[a][k] = lo + hi;  // the translation sum x[a][0] is never used
           x[a][k | (1 << b)] = hi - lo;
         }
   T y[3][8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t)
+  for (int a = 0; a < 3; ++a) y[a][0] = T(0);
 #pragma unroll
-    for (int a2 = 0; a2 < 3; ++a2) {
-      T acc = W[t * 9 + a2 * 3 + 0] * x[0][t ^ 1];
-      acc = fma(W[t * 9 + a2 * 3 + 1], x[1][t ^ 2], acc);
-      acc = fma(W[t * 9 + a2 * 3 + 2], x[2][t ^ 4], acc);
-      y[a2][t ^ (1 << a2)] = acc;
+  for (int h = 0; h < 2; ++h) {  // t = 0 and t = 7
+    const int t = 7 * h;
+    const T dm = C[2 * h], o = C[2 * h + 1];
+    const T x0 = x[0][t ^ 1], x1 = x[1][t ^ 2], x2 = x[2][t ^ 4];
+    const T os = o * (x0 + x1 + x2);
+    y[0][t ^ 1] = fma(dm, x0, os);
+    y[1][t ^ 2] = fma(dm, x1, os);
+    y[2][t ^ 4] = fma(dm, x2, os);
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const int i = other_lo(m), j = other_hi(m);
+    {
+      const int t = 1 << m;
+      cptr_t<T> B = C + 4 + 4 * m;
+      const T xi = x[i][t ^ (1 << i)], xj = x[j][t ^ (1 << j)];
+      y[i][t ^ (1 << i)] = fma(B[1], xj, B[0] * xi);
+      y[j][t ^ (1 << j)] = fma(B[3], xj, B[2] * xi);
     }
+    {
+      const int t = 7 ^ (1 << m);
+      cptr_t<T> B = C + 16 + 5 * m;
+      const T xi = x[i][t ^ (1 << i)], xj = x[j][t ^ (1 << j)];
+      y[i][t ^ (1 << i)] = fma(B[1], xj, B[0] * xi);
+      y[j][t ^ (1 << j)] = fma(B[3], xj, B[2] * xi);
+      y[m][t ^ (1 << m)] = B[4] * x[m][t ^ (1 << m)];
+    }
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -82,6 +113,50 @@ __device__ __forceinline__ void walsh8_apply(cptr_t<T> W, const T (&ue)[24], T (
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int k = 0; k < 8; ++k) fe[3 * k + a] = y[a][k];
+}
+
+// Staged displacement of a local node: FP32 products keep 4 floats per node (x, y, z, pad)
+// so one 16-byte read fetches it; FP64 products 3 doubles.
+template <bool FP32>
+struct LdsNode {
+  static constexpr int stride = FP32 ? 4 : 3;
+};
+
+// A regular 8-node cell of a kind-1 item: gather, structured Walsh product with the
+// class-scaled table, FP64 LDS atomics into the rows of owned corners.
+template <bool FP32>
+__device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, int lane, int n_own,
+                                      const typename LdsType<FP32>::T* __restrict__ ul, double* __restrict__ fl) {
+  using T = typename LdsType<FP32>::T;
+  const uint4 q = load_global(as_global(reinterpret_cast<const uint4*>(a.lidx)) + ((it.lidx0 >> 3) + lane));
+  const int li[8] = {(int)(q.x & 0xFFFFu), (int)(q.x >> 16), (int)(q.y & 0xFFFFu), (int)(q.y >> 16),
+                     (int)(q.z & 0xFFFFu), (int)(q.z >> 16), (int)(q.w & 0xFFFFu), (int)(q.w >> 16)};
+  T ue[24];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if constexpr (FP32) {
+      const float4 v = reinterpret_cast<const float4*>(ul)[li[c]];
+      ue[3 * c + 0] = v.x;
+      ue[3 * c + 1] = v.y;
+      ue[3 * c + 2] = v.z;
+    } else {
+      ue[3 * c + 0] = ul[3 * li[c] + 0];
+      ue[3 * c + 1] = ul[3 * li[c] + 1];
+      ue[3 * c + 2] = ul[3 * li[c] + 2];
+    }
+  }
+  T fe[24];
+  walsh8_sym<T>(as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64) + it.koff, ue, fe);
+  const uint32_t mask = it.mask;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (!((mask >> c) & 1u)) continue;  // uniform in the wave
+    if (li[c] >= n_own) continue;
+    double* fp = fl + 3 * li[c];
+    atomicAdd(fp + 0, (double)fe[3 * c + 0]);
+    atomicAdd(fp + 1, (double)fe[3 * c + 1]);
+    atomicAdd(fp + 2, (double)fe[3 * c + 2]);
+  }
 }
 
 // The block's tile: which mesh (single or batched launch), its argument block for
@@ -107,8 +182,8 @@ __device__ __forceinline__ bool block_tile(const MeshRef& single, const MeshRef*
   return true;
 }
 
-// Generic cell of NN nodes (any pattern): orientation per cell, dense master matrix
-// (or the Walsh form for the 8-node pattern), scale s_e per cell.
+// Generic cell of NN nodes (any pattern): orientation per cell, dense master matrix,
+// scale s_e per cell.
 template <int NN, bool FP32>
 __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it, int lane, int n_own,
                                           const typename LdsType<FP32>::T* __restrict__ ul,
@@ -131,34 +206,18 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
   {
     T rx = 0, ry = 0, rz = 0;
     if constexpr (FP32) {
-      const T* q0 = ul + 3 * li[0];
+      const T* q0 = ul + LdsNode<FP32>::stride * li[0];
       rx = q0[0];
       ry = q0[1];
       rz = q0[2];
     }
 #pragma unroll
     for (int k = 0; k < NN; ++k) {
-      const T* q = ul + 3 * li[k];
+      const T* q = ul + LdsNode<FP32>::stride * li[k];
       const T x = q[0] - rx, y = q[1] - ry, z = q[2] - rz;
       ue[3 * k + 0] = (T)s0 * pick3t<T>(p0, x, y, z);
       ue[3 * k + 1] = (T)s1 * pick3t<T>(p1, x, y, z);
       ue[3 * k + 2] = (T)s2 * pick3t<T>(p2, x, y, z);
-    }
-  }
-  if constexpr (NN == 8) {
-    if (it.koff == a.walsh_koff) {  // uniform in the wave
-      T fe[24];
-      walsh8_apply<T>(as_const(FP32 ? (const T*)a.W32 : (const T*)a.W64), ue, fe);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        if (!((mask >> k) & 1u)) continue;
-        if (li[k] >= n_own) continue;
-        // forces are summed in FP64 (LDS FP64 atomics are also the fast ones here)
-        atomicAdd(fl + 3 * li[k] + p0, s0 * se * (double)fe[3 * k + 0]);
-        atomicAdd(fl + 3 * li[k] + p1, s1 * se * (double)fe[3 * k + 1]);
-        atomicAdd(fl + 3 * li[k] + p2, s2 * se * (double)fe[3 * k + 2]);
-      }
-      return;
     }
   }
   cptr_t<T> Kp = as_const(FP32 ? (const T*)(a.K32 + it.koff) : (const T*)(a.K64 + it.koff));
@@ -211,9 +270,37 @@ __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile&
   }
 }
 
-// Tiles with cells of any pattern.  LDS: the owned forces (FP64), then u of the local nodes,
-// 3 values per node: FP64 for FP64 products; for FP32 products u minus the displacement of
-// the tile's first owned node, in FP32.
+// Stage u_n of the tile's local nodes in LDS (owned nodes first, then the tile's node list)
+// and clear the owned forces.  FP32 products keep u minus the displacement of the tile's
+// first owned node, so that only variations across the tile are rounded.
+template <bool FP32>
+__device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& tile, typename LdsType<FP32>::T* ul,
+                                           double* fl, int tid, int nt) {
+  gptr_t<double> u = as_global(a.u);
+  gptr_t<int32_t> nodelist = as_global(a.nodelist);
+  const int n_own = tile.n_own;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  if constexpr (FP32) {
+    r0 = u[3 * tile.own0 + 0];
+    r1 = u[3 * tile.own0 + 1];
+    r2 = u[3 * tile.own0 + 2];
+  }
+  for (int l = tid; l < tile.n_local; l += nt) {
+    const int64_t g = l < n_own ? tile.own0 + l : (int64_t)nodelist[tile.node0 + l - n_own];
+    const double x = u[3 * g + 0], y = u[3 * g + 1], z = u[3 * g + 2];
+    if constexpr (FP32) {
+      reinterpret_cast<float4*>(ul)[l] = make_float4((float)(x - r0), (float)(y - r1), (float)(z - r2), 0.0f);
+    } else {
+      ul[3 * l + 0] = x;
+      ul[3 * l + 1] = y;
+      ul[3 * l + 2] = z;
+    }
+  }
+  for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0;
+}
+
+// Tiles with cells of any pattern: kind-1 items take the 8-node path, the others the
+// dense product of their pattern.  LDS: the owned forces (FP64), then the staged u.
 template <bool FP32>
 __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef* __restrict__ refs,
                                                   const TileWork* __restrict__ work, int64_t first, int64_t count,
@@ -224,24 +311,12 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
   int64_t ti, step;
   if (!block_tile(single, refs, work, first, count, k, a, ti, step)) return;
   const OwnerTile tile = load_const(as_const(a.tiles) + ti);
-  const int n_own = tile.n_own, n_local = tile.n_local;
+  const int n_own = tile.n_own;
   double* fl = lds;
   T* ul = (T*)(lds + 3 * (int64_t)n_own);
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  gptr_t<double> u = as_global(a.u);
-  gptr_t<int32_t> nodelist = as_global(a.nodelist);
-  double ref[3] = {0.0, 0.0, 0.0};
-  if constexpr (FP32) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ref[c] = u[3 * tile.own0 + c];
-  }
-  for (int i = tid; i < 3 * n_local; i += nt) {
-    const int l = i / 3, c = i - 3 * l;
-    const int64_t g = l < n_own ? tile.own0 + l : (int64_t)nodelist[tile.node0 + l - n_own];
-    ul[i] = (T)(u[3 * g + c] - ref[c]);
-  }
-  for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0;
+  tile_stage<FP32>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
   // the wave index is uniform in a wave: say so, so item fields (and K_p) come through scalar loads
@@ -251,6 +326,10 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
   for (int w = wave; w < tile.n_items; w += n_waves) {
     const CellItem it = load_const(items + w);
     if (lane >= it.count) continue;
+    if (it.kind == 1) {
+      cell8<FP32>(a, it, lane, n_own, ul, fl);
+      continue;
+    }
 #define SBFEM_TCASE(N) \
   case N:              \
     tile_cell<N, FP32>(a, it, lane, n_own, ul, fl); \
@@ -266,16 +345,13 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
 #undef SBFEM_TCASE
   }
   __syncthreads();
+  // FP64 staging keeps u_n of the owned nodes at the start of ul (owned nodes come first)
   tile_update<FP32>(a, tile, fl, (const double*)ul, force_only, tid, nt);
 }
 
 // Tiles whose cells are all regular 8-node cells in identity orientation (the master
 // matrix is invariant under the 48 cube transformations, so the set-up maps every such
-// cell onto it without a transformation).  Per cell: one 16-byte record of local node
-// indices, the Walsh-form product with the blocks pre-scaled by the item's scale class,
-// FP64 LDS atomics for the owned rows.  LDS: owned forces (FP64), then u of the local
-// nodes: FP32 products 4 floats per node (x, y, z minus the tile reference, pad) so
-// one 16-byte read fetches a node; FP64 products 3 doubles per node.
+// cell onto it without a transformation): only kind-1 items.
 template <bool FP32>
 __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
                                                    const TileWork* __restrict__ work, int64_t first,
@@ -286,73 +362,23 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   int64_t ti, step;
   if (!block_tile(single, refs, work, first, count, k, a, ti, step)) return;
   const OwnerTile tile = load_const(as_const(a.tiles) + ti);
-  const int n_own = tile.n_own, n_local = tile.n_local;
+  const int n_own = tile.n_own;
   double* fl = lds;
   T* ul = (T*)(lds + 3 * (int64_t)n_own);
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  gptr_t<double> u = as_global(a.u);
-  gptr_t<int32_t> nodelist = as_global(a.nodelist);
-  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  if constexpr (FP32) {
-    r0 = u[3 * tile.own0 + 0];
-    r1 = u[3 * tile.own0 + 1];
-    r2 = u[3 * tile.own0 + 2];
-  }
-  for (int l = tid; l < n_local; l += nt) {
-    const int64_t g = l < n_own ? tile.own0 + l : (int64_t)nodelist[tile.node0 + l - n_own];
-    const double x = u[3 * g + 0], y = u[3 * g + 1], z = u[3 * g + 2];
-    if constexpr (FP32) {
-      reinterpret_cast<float4*>(ul)[l] = make_float4((float)(x - r0), (float)(y - r1), (float)(z - r2), 0.0f);
-    } else {
-      ul[3 * l + 0] = x;
-      ul[3 * l + 1] = y;
-      ul[3 * l + 2] = z;
-    }
-  }
-  for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0;
+  tile_stage<FP32>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int n_waves = nt >> 6;
   cptr_t<CellItem> items = as_const(a.items) + tile.item0;
-  gptr_t<uint4> lrec = as_global(reinterpret_cast<const uint4*>(a.lidx));
-  cptr_t<T> Ws = as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64);
   for (int w = wave; w < tile.n_items; w += n_waves) {
     const CellItem it = load_const(items + w);
     if (lane >= it.count) continue;
-    const uint4 q = load_global(lrec + ((it.lidx0 >> 3) + lane));
-    const int li[8] = {(int)(q.x & 0xFFFFu), (int)(q.x >> 16), (int)(q.y & 0xFFFFu), (int)(q.y >> 16),
-                       (int)(q.z & 0xFFFFu), (int)(q.z >> 16), (int)(q.w & 0xFFFFu), (int)(q.w >> 16)};
-    T ue[24];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      if constexpr (FP32) {
-        const float4 v = reinterpret_cast<const float4*>(ul)[li[c]];
-        ue[3 * c + 0] = v.x;
-        ue[3 * c + 1] = v.y;
-        ue[3 * c + 2] = v.z;
-      } else {
-        ue[3 * c + 0] = ul[3 * li[c] + 0];
-        ue[3 * c + 1] = ul[3 * li[c] + 1];
-        ue[3 * c + 2] = ul[3 * li[c] + 2];
-      }
-    }
-    T fe[24];
-    walsh8_apply<T>(Ws + it.koff, ue, fe);
-    const uint32_t mask = it.mask;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      if (!((mask >> c) & 1u)) continue;  // uniform in the wave
-      if (li[c] >= n_own) continue;
-      double* fp = fl + 3 * li[c];
-      atomicAdd(fp + 0, (double)fe[3 * c + 0]);
-      atomicAdd(fp + 1, (double)fe[3 * c + 1]);
-      atomicAdd(fp + 2, (double)fe[3 * c + 2]);
-    }
+    cell8<FP32>(a, it, lane, n_own, ul, fl);
   }
   __syncthreads();
-  // FP64 staging keeps u_n of the owned nodes at the start of ul (owned nodes come first)
   tile_update<FP32>(a, tile, fl, (const double*)ul, force_only, tid, nt);
 }
 

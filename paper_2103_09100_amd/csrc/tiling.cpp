@@ -7,11 +7,12 @@
 // into wave-sized items of one pattern and one row mask so that the master
 // matrix and the row selection are uniform within a wave.
 //
-// Tiles whose cells are all regular 8-node cells (pattern p8, identity
-// orientation) are laid out for the dedicated kernel: items of one scale class
-// (level, material) so the pre-scaled Walsh blocks are uniform in a wave, full
-// waves (cells sorted by row mask, the item's mask is the union), and the eight
-// local node indices of a cell stored together (16 bytes, lane-major).
+// Regular 8-node cells (pattern p8, identity orientation) form kind-1 items:
+// one scale class (level, material) per item so the pre-scaled Walsh table is
+// uniform in a wave, full waves (cells sorted by row mask and then in cell
+// order, the item's mask is the union), and the eight local node indices of a
+// cell stored together (16 bytes, lane-major).  Tiles with only such cells run
+// the dedicated 8-node kernel.
 #include <algorithm>
 #include <thread>
 #include <unordered_map>
@@ -120,48 +121,35 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
       if (in.p8 < 0 || in.pattern[c] != in.p8) r.pure8 = false;
       recs.push_back({(int32_t)j, mask, (int32_t)in.pattern[c]});
     }
-    if (r.pure8) {
-      // one scale class per item, cells sorted by row mask, full waves with the union mask
-      for (auto& rc : recs) rc.pattern = cls[cells[rc.c]];
-      std::sort(recs.begin(), recs.end(), [](const CellRec& a, const CellRec& b) {
-        return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
-      });
+    // regular 8-node cells (every cell of a pure tile): kind-1 items of one scale class, cells
+    // sorted by row mask and then in cell order, full waves with the union mask
+    std::vector<CellRec> r8, rg;
+    for (const auto& rc : recs) {
+      if (in.p8 >= 0 && in.pattern[cells[rc.c]] == in.p8)
+        r8.push_back({rc.c, rc.mask, cls[cells[rc.c]]});
+      else
+        rg.push_back(rc);
+    }
+    auto by_key = [](const CellRec& a, const CellRec& b) {
+      return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
+    };
+    std::stable_sort(r8.begin(), r8.end(), by_key);
+    std::stable_sort(rg.begin(), rg.end(), by_key);
+    // generic items: group by (pattern, row mask); small groups of one pattern share an item
+    const size_t kMerge = 16;
+    std::vector<std::vector<CellRec>> groups;
+    {
       size_t i0 = 0;
-      while (i0 < recs.size()) {
-        size_t i1 = i0;
-        while (i1 < recs.size() && i1 - i0 < (size_t)kWave && recs[i1].pattern == recs[i0].pattern) ++i1;
-        CellItem it{};
-        it.lidx0 = (int64_t)r.lidx.size();
-        it.cell0 = 0;
-        it.koff = 72 * (int64_t)recs[i0].pattern;
-        it.nn = 8;
-        it.count = (int32_t)(i1 - i0);
-        it.mask = 0;
-        for (size_t b = i0; b < i1; ++b) {
-          it.mask |= recs[b].mask;
-          for (int k = 0; k < 8; ++k) r.lidx.push_back(li_flat[li_off[recs[b].c] + k]);
-        }
-        r.items.push_back(it);
-        i0 = i1;
-      }
-    } else {
-      // group by (pattern, row mask); small groups of one pattern share an item with the union mask
-      std::sort(recs.begin(), recs.end(), [](const CellRec& a, const CellRec& b) {
-        return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
-      });
-      const size_t kMerge = 16;
-      size_t i0 = 0;
-      std::vector<std::vector<CellRec>> groups;
       std::vector<CellRec> small;
       int32_t small_pat = -1;
       auto flush_small = [&] {
         if (!small.empty()) groups.push_back(small);
         small.clear();
       };
-      while (i0 < recs.size()) {
+      while (i0 < rg.size()) {
         size_t i1 = i0;
-        while (i1 < recs.size() && recs[i1].pattern == recs[i0].pattern && recs[i1].mask == recs[i0].mask) ++i1;
-        std::vector<CellRec> g(recs.begin() + i0, recs.begin() + i1);
+        while (i1 < rg.size() && rg[i1].pattern == rg[i0].pattern && rg[i1].mask == rg[i0].mask) ++i1;
+        std::vector<CellRec> g(rg.begin() + i0, rg.begin() + i1);
         if (g.size() < kMerge) {
           if (small_pat != g[0].pattern) flush_small();
           small_pat = g[0].pattern;
@@ -172,31 +160,56 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
         i0 = i1;
       }
       flush_small();
-      for (auto& g : groups) {
-        for (size_t a = 0; a < g.size(); a += kWave) {
-          const size_t cnt = std::min<size_t>(kWave, g.size() - a);
-          CellItem it{};
-          const int32_t pid = g[a].pattern;
-          const int nn = in.pattern_ndof[pid] / 3;
-          it.lidx0 = (int64_t)r.lidx.size();
-          it.cell0 = (int64_t)r.orient.size();
-          it.koff = in.pattern_koff[pid];
-          it.nn = nn;
-          it.count = (int32_t)cnt;
-          it.mask = 0;
-          for (size_t b = 0; b < cnt; ++b) it.mask |= g[a + b].mask;
-          for (int k = 0; k < nn; ++k)
-            for (size_t b = 0; b < cnt; ++b) r.lidx.push_back(li_flat[li_off[g[a + b].c] + k]);
-          for (size_t b = 0; b < cnt; ++b) {
-            const int32_t c = cells[g[a + b].c];
-            r.orient.push_back(in.orient[c]);
-            r.level.push_back(in.level[c]);
-            r.material.push_back(in.material[c]);
-          }
-          r.items.push_back(it);
+    }
+    for (auto& g : groups) {
+      for (size_t a = 0; a < g.size(); a += kWave) {
+        const size_t cnt = std::min<size_t>(kWave, g.size() - a);
+        CellItem it{};
+        const int32_t pid = g[a].pattern;
+        const int nn = in.pattern_ndof[pid] / 3;
+        it.lidx0 = (int64_t)r.lidx.size();
+        it.cell0 = (int64_t)r.orient.size();
+        it.koff = in.pattern_koff[pid];
+        it.nn = nn;
+        it.count = (int32_t)cnt;
+        it.mask = 0;
+        it.kind = 0;
+        for (size_t b = 0; b < cnt; ++b) it.mask |= g[a + b].mask;
+        for (int k = 0; k < nn; ++k)
+          for (size_t b = 0; b < cnt; ++b) r.lidx.push_back(li_flat[li_off[g[a + b].c] + k]);
+        for (size_t b = 0; b < cnt; ++b) {
+          const int32_t c = cells[g[a + b].c];
+          r.orient.push_back(in.orient[c]);
+          r.level.push_back(in.level[c]);
+          r.material.push_back(in.material[c]);
         }
+        r.items.push_back(it);
       }
     }
+    // lane-major records start at a multiple of 8 entries (16 bytes)
+    while (r.lidx.size() % 8) r.lidx.push_back(0);
+    {
+      size_t i0 = 0;
+      while (i0 < r8.size()) {
+        size_t i1 = i0;
+        while (i1 < r8.size() && i1 - i0 < (size_t)kWave && r8[i1].pattern == r8[i0].pattern) ++i1;
+        CellItem it{};
+        it.lidx0 = (int64_t)r.lidx.size();
+        it.cell0 = 0;
+        it.koff = (int64_t)kWalshC * r8[i0].pattern;
+        it.nn = 8;
+        it.count = (int32_t)(i1 - i0);
+        it.mask = 0;
+        it.kind = 1;
+        for (size_t b = i0; b < i1; ++b) {
+          it.mask |= r8[b].mask;
+          for (int k = 0; k < 8; ++k) r.lidx.push_back(li_flat[li_off[r8[b].c] + k]);
+        }
+        r.items.push_back(it);
+        i0 = i1;
+      }
+    }
+    while (r.lidx.size() % 8) r.lidx.push_back(0);  // every tile's records start 16-byte aligned
     for (int64_t n = own0; n < own1; ++n)
       for (int a = 0; a < 3; ++a) {
         auto it = bmap.find(3 * n + a);
