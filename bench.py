@@ -9,8 +9,10 @@ every cell, central-difference update of every dof.
 Timed: K steps after W warm-up steps, bracketed by torch.cuda.synchronize(),
 with HIP events on the stream the library launches on.  The headline value
 is the FP32-product / FP64-state path; the plain FP64 path (and the colour
-assembly) are timed beside it.  A second, event-instrumented pass gives the
-average duration per launch of each kernel class for the roofline figure.
+assembly) are timed beside it.  HIP events that the library records around
+each launch on the same stream, in the same timed region, give the average
+duration per launch of each kernel class for the roofline figure; the
+algorithmic bytes per launch come from the library's layout report.
 
 Serving (reported beside the throughput): a Poisson stream of 256 requests
 (mean 20/s) of seeded inclusion meshes of 1e4-5e6 dofs (log-uniform) with
@@ -42,28 +44,109 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(mesh, pid_nodes):
-    """Bytes the method must move per step (see the measurement notes):
-    per dof u_n, u_{n-1}, M^-1 read and u_{n+1} written (8 B each); per cell
-    its node ids (4 B each) and orientation, level, material (1 B each);
-    per load entry index + value."""
-    n_dof = mesh.n_dof
-    conn_bytes = 4 * int(mesh.conn.shape[0])
-    cell_bytes = 3 * mesh.n_cells
-    step = 32 * n_dof + conn_bytes + cell_bytes + 16 * len(mesh.load_dof)
-    # the 8-node element kernel: its cells' ids and metadata, and u_n of the nodes it reads
-    is8 = pid_nodes == 8
-    c8 = int(is8.sum())
-    mark = np.zeros(mesh.n_nodes, dtype=bool)
-    ptr = mesh.conn_ptr
-    cells8 = np.flatnonzero(is8)
-    # 8-node cells have 8 consecutive entries
-    idx = (ptr[cells8][:, None] + np.arange(8)[None, :]).ravel()
-    mark[mesh.conn[idx]] = True
-    nodes8 = int(mark.sum())
-    ebe8 = c8 * (4 * 8 + 3) + 24 * nodes8
-    update = 32 * n_dof
-    return dict(step=step, element_8node=ebe8, update=update, cells_8node=c8, nodes_8node=nodes8)
+def algorithmic_bytes(mesh):
+    """Bytes the method must move per step: per dof u_n, u_{n-1}, M^-1 read and u_{n+1}
+    written (8 B each); per cell its node ids (4 B each) and orientation, level, material
+    (1 B each); per load entry index + value (16 B)."""
+    return 32 * mesh.n_dof + 4 * int(mesh.conn.shape[0]) + 3 * mesh.n_cells + 16 * len(mesh.load_dof)
+
+
+def kernel_sources_hash():
+    """SHA-256 over the library's kernel and host sources (names and contents)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2103_09100_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def _kernel_short(name):
+    import re
+    m = re.search(r"sbfem::(\w+(?:<[^>]*>)?)\(", name)
+    return m.group(1) if m else name.split("(")[0][:60]
+
+
+def summarise_counters(fetch_dir, write_dir, out, header):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of every kernel in two rocprofv3 --pmc runs,
+    with the scale factors that a plain 1 GiB read + 1 GiB write elementwise kernel gives."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def per_kernel(d, counter):
+        acc = defaultdict(lambda: defaultdict(float))
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") != counter:
+                    continue
+                acc[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "AUnaryFunctor" in k]
+    if not copy:
+        raise SystemExit("no copy kernel in the fetch run (run the bench with --copy-probe)")
+    copy_bytes = 1 << 30
+    lines = [f"# {l}" for l in header] + [
+        f"kernel_sources_sha256: {kernel_sources_hash()}",
+        f"copy_kernel: elementwise y = 1.0 * x over 2^28 floats (reads {copy_bytes} B, writes {copy_bytes} B)",
+        f"copy_fetch_kib: {fetch[copy[0]]:.1f}",
+        f"copy_write_kib: {write[copy[0]]:.1f}",
+        f"fetch_scale: {copy_bytes / 1024 / fetch[copy[0]]:.6f}",
+        f"write_scale: {copy_bytes / 1024 / write[copy[0]]:.6f}",
+    ]
+    for k in sorted(fetch):
+        if "sbfem::" in k:
+            lines.append(f"fetch_kib[{_kernel_short(k)}]: {fetch[k]:.1f}")
+    for k in sorted(write):
+        if "sbfem::" in k:
+            lines.append(f"write_kib[{_kernel_short(k)}]: {write[k]:.1f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarise_trace(trace_dir, out, header):
+    """Kernel statistics of a rocprofv3 --kernel-trace --stats run (per kernel: dispatches,
+    average and total duration)."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    lines = [f"# {l}" for l in header] + [f"kernel_sources_sha256: {kernel_sources_hash()}",
+                                          "kernel | calls | average ns | total ns | percent"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{_kernel_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']):.0f} | "
+                     f"{float(r['TotalDurationNs']):.0f} | {float(r['Percentage']):.2f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def counter_traffic(kernel, path=os.path.join(ROOT, "profiles", "cfg3_owner_tiles_hbm_counters.txt")):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary, scaled by the copy
+    kernel's factors; None if there is none or the kernel sources changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    try:
+        f = float(vals[f"fetch_kib[{kernel}]"]) * 1024 * float(vals["fetch_scale"])
+        w = float(vals[f"write_kib[{kernel}]"]) * 1024 * float(vals["write_scale"])
+    except KeyError:
+        return None
+    return f + w
 
 
 def make_mesh(name):
@@ -78,26 +161,23 @@ def make_mesh(name):
 
 
 def time_mode(sim, torch, stream, steps, warmup):
+    """Wall time per step over `steps` steps (events around the whole region) and, from HIP
+    events the library records around each launch on the same stream in the same region,
+    the average duration of each kernel class."""
     with torch.cuda.stream(stream):
         sim.step(warmup)
         torch.cuda.synchronize()
+        sim.gpu.profile(True)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
         sim.step(steps)
         b.record(stream)
         torch.cuda.synchronize()
-    return a.elapsed_time(b) / steps
-
-
-def profile_mode(sim, torch, stream, steps):
-    sim.gpu.profile(True)
-    with torch.cuda.stream(stream):
-        sim.step(steps)
-        torch.cuda.synchronize()
     prof = sim.gpu.profile_read()
     sim.gpu.profile(False)
-    return {k: dict(ms_total=v[0], launches=v[1], ms_avg=(v[0] / v[1] if v[1] else 0.0)) for k, v in prof.items()}
+    kernels = {k: dict(ms_total=v[0], launches=v[1], ms_avg=(v[0] / v[1] if v[1] else 0.0)) for k, v in prof.items()}
+    return a.elapsed_time(b) / steps, kernels
 
 
 def cpu_baseline(seconds=12.0):
@@ -200,14 +280,25 @@ def main():
     ap.add_argument("--serve-prod", default="fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for the HBM byte counters)")
+    ap.add_argument("--summarise", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    help="write the HBM counter summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarise-trace", nargs=2, metavar=("TRACE_DIR", "OUT"),
+                    help="write the kernel statistics of a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--summary-header", action="append", default=[],
+                    help="comment line for --summarise / --summarise-trace (workload, commands)")
     args = ap.parse_args()
+    if args.summarise:
+        summarise_counters(*args.summarise, header=args.summary_header)
+        return
+    if args.summarise_trace:
+        summarise_trace(*args.summarise_trace, header=args.summary_header)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               f"path is not part of this build", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_2103_09100_amd import library
     from paper_2103_09100_amd.solver import Simulation
 
     if args.serve_only:
@@ -222,10 +313,7 @@ def main():
     mesh, desc = make_mesh(args.config)
     log(f"[bench] mesh {args.config}: {mesh.n_cells} cells, {mesh.n_nodes} nodes, {mesh.n_dof} dofs "
         f"({time.time() - t0:.0f} s)")
-    pid, _, _ = library.canonicalise(mesh)
-    nn = library.pt.table().n_nodes[pid]
-    ab = algorithmic_bytes(mesh, nn)
-    del pid
+    ab = dict(step=algorithmic_bytes(mesh))
     log(f"[bench] algorithmic bytes/step {ab['step'] / 1e9:.3f} GB ({ab['step'] / mesh.n_dof:.1f} B/dof)")
 
     stream = torch.cuda.Stream()
@@ -247,10 +335,10 @@ def main():
         sim = Simulation(mesh, prod=prod, assembly=assembly, stream=stream.cuda_stream)
         log(f"[bench] {mode}: created in {time.time() - t1:.0f} s, dt={sim.dt:.4e}, "
             f"{sim.gpu.info()['n_colours']} colours, {sim.footprint / 1e9:.1f} GB, layout {sim.gpu.layout()}")
-        ms = time_mode(sim, torch, stream, n_steps, n_warm)
-        prof = profile_mode(sim, torch, stream, n_steps)
+        ms, prof = time_mode(sim, torch, stream, n_steps, n_warm)
         finals[mode] = sim.u()
-        results[mode] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), kernels=prof, steps=n_steps)
+        results[mode] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), kernels=prof, steps=n_steps,
+                             layout=sim.gpu.layout())
         log(f"[bench] {mode}: {ms:.3f} ms/step, {results[mode]['value']:.3e} DOF-steps/s, "
             + ", ".join(f"{k} {v['ms_avg']:.3f} ms x{v['launches']}" for k, v in prof.items()))
         sim.close()
@@ -261,7 +349,14 @@ def main():
     fp64 = next((m for m in args.modes.split(",") if m.startswith("fp64:")), None)
     r = results[head]
     k8 = r["kernels"]["element_8node"]
-    achieved = ab["element_8node"] / (k8["ms_avg"] * 1e-3) / 1e9 if k8["ms_avg"] > 0 else 0.0
+    lay = r["layout"]
+    alg8 = lay["alg_bytes_8node"]
+    if lay["alg_bytes_8node"] + lay["alg_bytes_other"] != ab["step"]:
+        log(f"[bench] warning: per-kernel algorithmic bytes {lay['alg_bytes_8node'] + lay['alg_bytes_other']} "
+            f"!= step bytes {ab['step']}")
+    achieved = alg8 / (k8["ms_avg"] * 1e-3) / 1e9 if k8["ms_avg"] > 0 else 0.0
+    kname = "tiled_step8<true>" if head.startswith("fp32") else "tiled_step8<false>"
+    traffic = counter_traffic(kname)
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -278,12 +373,14 @@ def main():
         "config": {"workload": f"{args.config}: {desc}", "n_dof": mesh.n_dof, "n_cells": mesh.n_cells,
                    "product": head.split(":")[0], "state": "fp64", "assembly": head.split(":")[1],
                    "steps_per_call": args.steps},
-        "roofline": {"bound": "hbm", "kernel": "element kernel, 8-node cells", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "kernel": f"{kname}: owner tiles of 8-node cells (element forces + update)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
                      "step_achieved": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9,
                      "step_frac": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "alg_bytes_per_launch": ab["element_8node"], "alg_bytes_per_step": ab["step"],
-                     "avg_launch_ms": k8["ms_avg"]},
+                     "alg_bytes_per_launch": alg8, "alg_bytes_other_kernel": lay["alg_bytes_other"],
+                     "alg_bytes_per_step": ab["step"], "avg_launch_ms": k8["ms_avg"],
+                     "launches": k8["launches"]},
         "modes": {k: dict(ms_per_step=v["ms_per_step"], value=v["value"], steps=v["steps"],
                           kernels_ms_avg={c: d["ms_avg"] for c, d in v["kernels"].items()})
                   for k, v in results.items()},

@@ -184,7 +184,11 @@ sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches);
  * Layout statistics (diagnostics): vals[0..n_vals) receives, in order,
  *  0 owner tiles with 8-node cells only, 1 other owner tiles, 2 cell items,
  *  3 local node entries over all tiles, 4 cell entries over all tiles (cells
- *  touching several tiles count once per tile), 5 nodes owned per tile.
+ *  touching several tiles count once per tile), 5 nodes owned per tile,
+ *  6 and 7 algorithmic bytes per step of the 8-node-tile kernel and of the
+ *  other-tile kernel: 32 B per owned dof (u_n, u_{n-1}, M^-1 read, u_{n+1}
+ *  written), 4 B per node id + 3 B per cell for the cells whose lowest node the
+ *  kernel's tiles own, 16 B per load entry (eq. DnMdiag, Alg. 1 time loop).
  * Entries not available for the mesh's assembly are 0.
  */
 sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals);

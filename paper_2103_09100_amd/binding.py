@@ -225,7 +225,8 @@ class Mesh:
         _check(_lib.sbfem_mesh_info(self.handle, C.byref(b), C.byref(n), C.byref(c)))
         return dict(device_bytes=b.value, n_dof=n.value, n_colours=c.value)
 
-    LAYOUT = ("tiles_8node", "tiles_other", "items", "local_nodes", "cell_entries", "tile_nodes")
+    LAYOUT = ("tiles_8node", "tiles_other", "items", "local_nodes", "cell_entries", "tile_nodes",
+              "alg_bytes_8node", "alg_bytes_other")
 
     def layout(self):
         v = np.zeros(len(self.LAYOUT), dtype=np.int64)

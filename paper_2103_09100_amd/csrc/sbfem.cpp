@@ -165,7 +165,7 @@ struct sbfem_mesh {
   int32_t block_threads = 512;        // 8-node owner tiles
   int32_t block_threads_mixed = 256;  // owner tiles with larger cells
   bool walsh = true;
-  int64_t layout[6] = {0, 0, 0, 0, 0, 0};
+  int64_t layout[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -715,6 +715,25 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     for (int64_t t = 0; t < to.n_pure8; ++t)       // plus those of pure 8-node tiles
       for (int32_t w = 0; w < to.tiles[t].n_items; ++w) m->layout[4] += to.items[to.tiles[t].item0 + w].count;
     m->layout[5] = to.tile_nodes;
+    // algorithmic bytes per step of each kernel (the method's own traffic, whatever the layout):
+    // per owned dof u_n, u_{n-1}, M^-1 read and u_{n+1} written (8 B each); per cell its node
+    // ids (4 B each) and orientation, level, material (1 B each), counted in the tile that owns
+    // the cell's lowest node; per load entry 16 B
+    {
+      const int64_t tn = to.tile_nodes;
+      std::vector<char> pure((N + tn - 1) / tn, 0);
+      for (int64_t t = 0; t < to.n_pure8; ++t) pure[to.tiles[t].own0 / tn] = 1;
+      int64_t b8 = 0, bo = 0;
+      for (const auto& t : to.tiles) (pure[t.own0 / tn] ? b8 : bo) += 3 * (int64_t)t.n_own * 32;
+      for (int64_t c = 0; c < C; ++c) {
+        int32_t lo = iconn[cptr[c]];
+        for (int64_t i = cptr[c] + 1; i < cptr[c + 1]; ++i) lo = std::min(lo, iconn[i]);
+        (pure[lo / tn] ? b8 : bo) += 4 * (cptr[c + 1] - cptr[c]) + 3;
+      }
+      for (auto dof : bidx) (pure[(dof / 3) / tn] ? b8 : bo) += 16;
+      m->layout[6] = b8;
+      m->layout[7] = bo;
+    }
     ALLOC(otiles, to.tiles.size())
     ALLOC(items, to.items.size())
     ALLOC(lidx, to.lidx.size())
@@ -1149,7 +1168,7 @@ sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches) {
 
 sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals) {
   if (!m || (n_vals > 0 && !vals)) return fail(SBFEM_EINVAL, "null argument");
-  for (int i = 0; i < n_vals; ++i) vals[i] = i < 6 ? m->layout[i] : 0;
+  for (int i = 0; i < n_vals; ++i) vals[i] = i < 8 ? m->layout[i] : 0;
   return SBFEM_OK;
 }
 
