@@ -262,6 +262,70 @@ def serving(torch, args):
     return out
 
 
+def precision_sweep(torch, args):
+    """Products FP64/FP32/FP16/BF16 x state FP64/compensated FP32/FP32 on the cfg4 mesh.
+    Per combination: DOF-steps/s over a timed run; the max relative displacement error over
+    the sampled steps of a --sweep-steps run against the FP64/FP64 path (itself pinned to the
+    oracle by the tests; the oracle does not run at this size here); and the drift of the
+    discrete energy H_{n+1/2} over the free-vibration phase after the load has ended (the
+    undamped scheme keeps it constant), evaluated on the host in FP64 with the library's
+    FP64 operator and lumped mass."""
+    from meshgen import configs
+    from paper_2103_09100_amd.solver import Simulation
+    mesh = configs.cfg4(n_steps=args.sweep_steps)
+    log(f"[sweep] cfg4 mesh: {mesh.n_cells} cells, {mesh.n_dof} dofs")
+    stream = torch.cuda.Stream()
+    n_total, every = args.sweep_steps, 100
+    evaluator = Simulation(mesh, prod="fp64", state="fp64", stream=stream.cuda_stream)
+    M = evaluator.gpu.read(3, stream.cuda_stream)[0]
+    dt = evaluator.dt
+    # the Ricker pulse is below 1e-12 P0 once (t - t1) / (t1 / 5) >= 8, i.e. for t >= 2.6 t1
+    assert mesh.load["kind"] == "ricker"
+    t_end = int(np.ceil(2.6 * mesh.load["t1"] / dt))
+    if t_end >= n_total - 2 * every:
+        raise SystemExit(f"the load lasts until step {t_end}: no free-vibration phase in {n_total} steps")
+    h_at = sorted(set(list(range(t_end + every - t_end % every, n_total + 1, 2 * every)) + [n_total]))
+
+    def energy(u, un):  # H_{n+1/2} from u_{n+1} = u, u_n = un
+        evaluator.write(un, un, 0)
+        f = evaluator.internal_force()
+        d = u - un
+        return 0.5 * (d @ (M * d)) / dt ** 2 + 0.5 * (u @ f)
+
+    ref_snaps, rows = {}, []
+    combos = [(p, st) for p in ("fp64", "fp32", "fp16", "bf16") for st in ("fp64", "kahan32", "fp32")]
+    for prod, state in combos:
+        sim = Simulation(mesh, prod=prod, state=state, stream=stream.cuda_stream)
+        ms, _ = time_mode(sim, torch, stream, args.sweep_time_steps, 5)
+        sim.close()
+        sim = Simulation(mesh, prod=prod, state=state, stream=stream.cuda_stream)
+        snaps, H = {}, []
+        done = 0
+        while done < n_total:
+            sim.step(every)
+            done += every
+            snaps[done] = sim.u()
+            if done in h_at:
+                u, n = sim.gpu.read(0, stream.cuda_stream)
+                un, _ = sim.gpu.read(1, stream.cuda_stream)
+                H.append(energy(u, un))
+        sim.close()
+        if (prod, state) == ("fp64", "fp64"):
+            ref_snaps = snaps
+        num = max(float(np.abs(snaps[k] - ref_snaps[k]).max()) for k in ref_snaps)
+        den = max(float(np.abs(ref_snaps[k]).max()) for k in ref_snaps)
+        H = np.array(H)
+        drift = float(np.abs(H - H[0]).max() / abs(H[0])) if len(H) > 1 else float("nan")
+        row = dict(product=prod, state=state, ms_per_step=ms, dof_steps_per_s=mesh.n_dof / (ms * 1e-3),
+                   e_max_vs_fp64=num / den, energy_drift=drift, energy_samples=len(H))
+        rows.append(row)
+        log(f"[sweep] {prod} products, {state} state: {ms:.3f} ms/step ({row['dof_steps_per_s']:.3e} DOF-steps/s), "
+            f"e_max vs FP64 {row['e_max_vs_fp64']:.3e}, energy drift {drift:.3e} ({len(H)} samples)")
+    evaluator.close()
+    return dict(workload=f"cfg4 sphere-band octree L4/8, {mesh.n_dof} dofs, {mesh.n_cells} cells",
+                steps=n_total, snapshot_every=every, load_ends_at_step=t_end, energy_steps=h_at, rows=rows)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +344,10 @@ def main():
     ap.add_argument("--serve-prod", default="fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for the HBM byte counters)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="precision sweep on the cfg4 mesh (products x state storage) instead of the benchmark")
+    ap.add_argument("--sweep-steps", type=int, default=2000)
+    ap.add_argument("--sweep-time-steps", type=int, default=200)
     ap.add_argument("--summarise", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
                     help="write the HBM counter summary of two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarise-trace", nargs=2, metavar=("TRACE_DIR", "OUT"),
@@ -300,6 +368,12 @@ def main():
 
     import torch
     from paper_2103_09100_amd.solver import Simulation
+
+    if args.sweep:
+        sw = precision_sweep(torch, args)
+        print(json.dumps({"metric": "precision sweep: DOF-steps/s, max relative displacement error vs FP64, "
+                                    "energy drift", "n_gpus": 1, "data": "synthetic", "sweep": sw}), flush=True)
+        return
 
     if args.serve_only:
         sv = serving(torch, args)

@@ -155,7 +155,9 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
 
 /*
  * Copy state to host memory host_out [3N] (FP64):
- *   which = 0: u_n, 1: u_{n-1}, 2: R_int(u_n) = sum_e s_e R_e^T K_p R_e u_e.
+ *   which = 0: u_n, 1: u_{n-1}, 2: R_int(u_n) = sum_e s_e R_e^T K_p R_e u_e (in the mesh's
+ *   product precision), 3: the lumped diagonal mass M (Sec. 3.3; FP64, fixed dofs included).
+ * Reduced state storage is widened to FP64 (a compensated pair as hi + lo).
  * *step (may be NULL) receives n.  Blocks until the copy has landed.
  */
 sbfem_status sbfem_read_state(sbfem_mesh* m, int32_t which, double* host_out, int64_t* step,

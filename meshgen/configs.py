@@ -225,7 +225,7 @@ def small_zoo(seed=0, n_steps=200):
     return m
 
 
-def cfg4(seed=0, n_steps=2000, delta=0.02):
+def cfg4(seed=0, n_steps=2000, delta=0.15):
     m = sphere_band_mesh(seed=seed, lcoarse=4, lfine=8, delta=delta)
     _run_params(m, fm=2.0, n_steps=n_steps)
     m.meta["name"] = "cfg4 sphere band L4/8"

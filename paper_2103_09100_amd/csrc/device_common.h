@@ -55,6 +55,48 @@ __device__ __forceinline__ T load_global(gptr_t<T> p) {
   return v;
 }
 
+// State storage (TiledArgs::state): FP64; FP32; or a compensated pair of FP32 values whose
+// sum carries the value (hi = fl32(v), lo = fl32(v - hi)), hi at p[i] and lo at p[ndof + i].
+// Arithmetic on the state is done in FP64 registers.
+__device__ __forceinline__ double state_load(const void* p, int32_t mode, int64_t ndof, int64_t i) {
+  if (mode == 0) return as_global((const double*)p)[i];
+  const gptr_t<float> q = as_global((const float*)p);
+  if (mode == 1) return (double)q[i];
+  return (double)q[i] + (double)q[ndof + i];
+}
+__device__ __forceinline__ void state_store(void* p, int32_t mode, int64_t ndof, int64_t i, double v) {
+  if (mode == 0) {
+    as_global_mut((double*)p)[i] = v;
+    return;
+  }
+  const gmut_t<float> q = as_global_mut((float*)p);
+  const float hi = (float)v;
+  q[i] = hi;
+  if (mode == 2) q[ndof + i] = (float)(v - (double)hi);
+}
+__device__ __forceinline__ double minv_load(const void* p, int32_t mode, int64_t i) {
+  return mode == 1 ? (double)as_global((const float*)p)[i] : as_global((const double*)p)[i];
+}
+
+// 16-bit product operands (values kept in FP32 registers; a product of two 16-bit values is
+// exact in FP32, so FMAs on them are 16-bit products with FP32 accumulation).
+__device__ __forceinline__ float round_fp16(float x) { return (float)(_Float16)x; }
+__device__ __forceinline__ float round_bf16(float x) {  // round to nearest even on the FP32 bits
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return __uint_as_float(b & 0xFFFF0000u);
+}
+__device__ __forceinline__ float round16(float x, int32_t mode) {
+  return mode == 1 ? round_fp16(x) : round_bf16(x);
+}
+// power of two that brings max |x| into [1, 2) (1 for x = 0): FP16 operands are scaled by it
+__device__ __forceinline__ float pow2_scale(float maxabs) {
+  if (!(maxabs > 0.0f)) return 1.0f;
+  int e;
+  (void)frexpf(maxabs, &e);  // maxabs = f 2^e, f in [0.5, 1)
+  return ldexpf(1.0f, 1 - e);
+}
+
 // orientation code -> axis permutation pi and signs s:  u_master[k][a] = s_a u[node][pi(a)]
 __device__ __forceinline__ void decode_orient(int code, int& p0, int& p1, int& p2,
                                               double& s0, double& s1, double& s2) {

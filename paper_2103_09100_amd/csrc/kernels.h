@@ -69,13 +69,16 @@ struct TiledArgs {
   const double* matE;
   double h0;
   const double* K64;
-  const float* K32;
+  const float* K32;     // FP32 products: K in FP32; 16-bit products: K rounded to FP16 / BF16, held in FP32
   const double* Ws64;   // 8-node cell: structured Walsh table times s_e, kWalshC per scale class
-  const float* Ws32;
-  const double* u;      // u_n
-  double* um1;          // u_{n-1} in, u_{n+1} out (owned nodes)
-  const double* minv;
+  const float* Ws32;    // (16-bit products: the unscaled table rounded to 16 bits, s_e in the last entry)
+  const void* u;        // u_n        (state storage, see `state`)
+  void* um1;            // u_{n-1} in, u_{n+1} out (owned nodes)
+  const void* minv;     // FP64, or FP32 with FP32 state
   double* f;            // force-only mode: R_int of owned dofs written here
+  int64_t ndof;         // dofs of the mesh (offset of the low parts of compensated state)
+  int32_t state;        // 0 FP64, 1 FP32, 2 compensated FP32 pair (hi at u[i], lo at u[ndof + i])
+  int32_t round16;      // 16-bit product operands: 0 none, 1 FP16 (per-cell power-of-two scale), 2 BF16
   LoadParams L;         // P(t) of the load vector
   double dt;
   double dt2;
@@ -172,5 +175,6 @@ hipError_t launch_update(const double* un, double* unm1, double* f, const double
                          double dt2, double c, hipStream_t s);
 hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t s);
 hipError_t launch_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s);
+hipError_t launch_finite32(const float* a, int64_t n, int32_t* flag, hipStream_t s);
 
 }  // namespace sbfem

@@ -49,7 +49,8 @@ __global__ void fill_kernel(double* __restrict__ a, int64_t n, double v) {
 }
 
 // flag[0] |= 1 if any entry is not finite
-__global__ void finite_kernel(const double* __restrict__ a, int64_t n, int32_t* __restrict__ flag) {
+template <class V>
+__global__ void finite_kernel(const V* __restrict__ a, int64_t n, int32_t* __restrict__ flag) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   bool bad = false;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -106,7 +107,12 @@ hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t s) {
 }
 
 hipError_t launch_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s) {
-  hipLaunchKernelGGL(finite_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, n, flag);
+  hipLaunchKernelGGL(finite_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, a, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_finite32(const float* a, int64_t n, int32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(finite_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, a, n, flag);
   return hipGetLastError();
 }
 

@@ -81,6 +81,43 @@ int corner_image(int k, const int pi[3], const double s[3]) {
   return n;
 }
 
+// 16-bit operand rounding on the host (round to nearest even), as the device does it
+float round_fp16(float x) { return (float)(_Float16)x; }
+float round_bf16(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  b &= 0xFFFF0000u;
+  float y;
+  std::memcpy(&y, &b, 4);
+  return y;
+}
+
+// State arrays in device storage form (sbfem_state): FP64; FP32; compensated FP32 pair with
+// hi = fl32(v) in [0, n) and lo = fl32(v - hi) in [n, 2n).
+int64_t state_bytes(int mode, int64_t n) { return n * (mode == SBFEM_STATE_FP32 ? 4 : 8); }
+std::vector<char> pack_state(int mode, const double* v, int64_t n) {
+  std::vector<char> raw(state_bytes(mode, n));
+  if (mode == SBFEM_STATE_FP64) {
+    std::memcpy(raw.data(), v, n * 8);
+  } else {
+    float* q = (float*)raw.data();
+    for (int64_t i = 0; i < n; ++i) {
+      q[i] = (float)v[i];
+      if (mode == SBFEM_STATE_KAHAN32) q[n + i] = (float)(v[i] - (double)q[i]);
+    }
+  }
+  return raw;
+}
+void unpack_state(int mode, const char* raw, int64_t n, double* v) {
+  if (mode == SBFEM_STATE_FP64) {
+    std::memcpy(v, raw, n * 8);
+    return;
+  }
+  const float* q = (const float*)raw;
+  for (int64_t i = 0; i < n; ++i) v[i] = (double)q[i] + (mode == SBFEM_STATE_KAHAN32 ? (double)q[n + i] : 0.0);
+}
+
 double load_time_host(const sbfem::LoadParams& L, double t) {
   if (L.kind == SBFEM_LOAD_RICKER) {
     const double tau = (t - L.t1) / (L.t1 / 5.0);
@@ -106,6 +143,8 @@ struct sbfem_patterns {
   std::vector<double> K, m, omega;
   double* dK64 = nullptr;
   float* dK32 = nullptr;
+  float* dK16 = nullptr;   // K rounded to FP16, held in FP32 (16-bit product operands)
+  float* dKb16 = nullptr;  // K rounded to BF16, held in FP32
   // 8-node pattern in the corner Walsh basis (8 blocks of 3x3), if its matrix has that structure
   int64_t walsh_koff = -1;
   // the 8-node pattern when its matrix is also invariant under the 48 cube transformations:
@@ -122,10 +161,10 @@ struct sbfem_mesh {
   double h0 = 1.0, dt = 0.0, alpha = 0.0;
   int prod = 0, state_mode = 0, assembly = 0;
   sbfem::LoadParams L{};
-  double* u = nullptr;
-  double* um1 = nullptr;
+  void* u = nullptr;     // state storage per state_mode: FP64, FP32 or compensated FP32 pair
+  void* um1 = nullptr;
   double* f = nullptr;
-  double* minv = nullptr;
+  void* minv = nullptr;  // FP64, or FP32 with FP32 state
   double* matE = nullptr;
   int32_t* conn = nullptr;
   uint8_t* orient = nullptr;
@@ -150,6 +189,7 @@ struct sbfem_mesh {
   int n_colours = 1;
   // internal node numbering (first touch along the cell order)
   std::vector<int32_t> int2ext;
+  std::vector<double> mdiag;  // lumped diagonal mass (internal numbering), for read_state
   // owner tiles
   sbfem::OwnerTile* otiles = nullptr;
   sbfem::CellItem* items = nullptr;
@@ -161,7 +201,7 @@ struct sbfem_mesh {
   sbfem::TiledArgs* d_args = nullptr;   // two argument blocks: (u=buf0, prev=buf1) and swapped
   double* dWs64 = nullptr;              // Walsh blocks times s_e per scale class (pure 8-node tiles)
   float* dWs32 = nullptr;
-  double* buf0 = nullptr;
+  void* buf0 = nullptr;
   int32_t block_threads = 512;        // 8-node owner tiles
   int32_t block_threads_mixed = 256;  // owner tiles with larger cells
   bool walsh = true;
@@ -187,9 +227,12 @@ sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
   if (d->load_nnz < 0 || (d->load_nnz > 0 && (!d->load_dof || !d->load_val)))
     return fail(SBFEM_EINVAL, "bad load vector");
   if (d->load_kind < 0 || d->load_kind > 2) return fail(SBFEM_EINVAL, "unknown load kind");
-  if (d->prod != SBFEM_PROD_FP64 && d->prod != SBFEM_PROD_FP32)
-    return fail(SBFEM_EINVAL, "product precision %d not available", d->prod);
-  if (d->state != SBFEM_STATE_FP64) return fail(SBFEM_EINVAL, "state storage %d not available", d->state);
+  if (d->prod < SBFEM_PROD_FP64 || d->prod > SBFEM_PROD_BF16)
+    return fail(SBFEM_EINVAL, "unknown product precision %d", d->prod);
+  if (d->state < SBFEM_STATE_FP64 || d->state > SBFEM_STATE_KAHAN32)
+    return fail(SBFEM_EINVAL, "unknown state storage %d", d->state);
+  if ((d->prod >= SBFEM_PROD_FP16 || d->state != SBFEM_STATE_FP64) && d->assembly != SBFEM_ASM_TILED)
+    return fail(SBFEM_EINVAL, "16-bit products and FP32 or compensated state need the tiled assembly");
   if (d->assembly != SBFEM_ASM_ATOMIC && d->assembly != SBFEM_ASM_COLOUR && d->assembly != SBFEM_ASM_TILED)
     return fail(SBFEM_EINVAL, "unknown assembly mode");
   if (d->tile_nodes < 0 || d->block_threads < 0 || d->block_threads_mixed < 0 ||
@@ -207,7 +250,8 @@ sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
 
 int64_t footprint_bytes(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t total_conn) {
   const int64_t ndof = 3 * d->n_nodes;
-  int64_t b = ndof * 8 * 4;                     // u, u_prev, f, minv
+  int64_t b = 2 * state_bytes(d->state, ndof) + ndof * 8;  // u, u_prev, f
+  b += ndof * (d->state == SBFEM_STATE_FP32 ? 4 : 8);       // minv
   b += total_conn * 4 + d->n_cells * 3;         // node ids, orientation, level, material
   b += ((d->n_cells + sbfem::kTile - 1) / sbfem::kTile + p->n * 64) * (int64_t)sizeof(sbfem::Tile);
   b += d->load_nnz * 16 + 256 * 8 + 64;
@@ -340,12 +384,23 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess) e = dalloc(&p->dK64, ko);
   if (e == hipSuccess) e = dalloc(&p->dK32, ko);
+  if (e == hipSuccess) e = dalloc(&p->dK16, ko);
+  if (e == hipSuccess) e = dalloc(&p->dKb16, ko);
+  std::vector<float> K16(ko), Kb16(ko);
+  for (int64_t i = 0; i < ko; ++i) {
+    K16[i] = round_fp16(K32[i]);
+    Kb16[i] = round_bf16(K32[i]);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(p->dK64, p->K.data(), ko * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(p->dK32, K32.data(), ko * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->dK16, K16.data(), ko * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->dKb16, Kb16.data(), ko * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     dfree(p->dK64);
     dfree(p->dK32);
+    dfree(p->dK16);
+    dfree(p->dKb16);
     delete p;
     return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "pattern upload: %s", hipGetErrorString(e));
   }
@@ -358,6 +413,8 @@ void sbfem_destroy_patterns(sbfem_patterns* p) {
   (void)hipSetDevice(p->device);
   dfree(p->dK64);
   dfree(p->dK32);
+  dfree(p->dK16);
+  dfree(p->dKb16);
   delete p;
 }
 
@@ -422,7 +479,7 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
 static sbfem::ElementArgs element_args(const sbfem_mesh* m) {
   sbfem::ElementArgs a;
   a.tiles = m->tiles;
-  a.u = m->u;
+  a.u = (const double*)m->u;  // the classic assemblies keep FP64 state
   a.f = m->f;
   a.conn = m->conn;
   a.orient = m->orient;
@@ -456,7 +513,7 @@ static sbfem::LaunchHook hook_of(sbfem_mesh* m) {
 }
 
 // f += R_int(u) over all colours (f must hold what it should be added to)
-static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const double* u, double* um1) {
+static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const void* u, void* um1) {
   sbfem::TiledArgs a{};
   a.tiles = m->otiles;
   a.n_tiles = m->n_pure8 + m->n_mixed;
@@ -470,13 +527,16 @@ static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const double* u, dou
   a.matE = m->matE;
   a.h0 = m->h0;
   a.K64 = m->P->dK64;
-  a.K32 = m->P->dK32;
+  a.K32 = m->prod == SBFEM_PROD_FP16 ? m->P->dK16 : (m->prod == SBFEM_PROD_BF16 ? m->P->dKb16 : m->P->dK32);
   a.Ws64 = m->dWs64;
   a.Ws32 = m->dWs32;
   a.u = u;
   a.um1 = um1;
   a.minv = m->minv;
   a.f = m->f;
+  a.ndof = m->ndof;
+  a.state = m->state_mode;
+  a.round16 = m->prod == SBFEM_PROD_FP16 ? 1 : (m->prod == SBFEM_PROD_BF16 ? 2 : 0);
   a.L = m->L;
   a.dt = m->dt;
   a.dt2 = m->dt * m->dt;
@@ -496,7 +556,7 @@ static sbfem::TiledLaunch tiled_launch(const sbfem_mesh* m, bool force_only) {
   L.single.parity = tiled_parity(m);
   L.n_pure8 = m->n_pure8;
   L.n_mixed = m->n_mixed;
-  L.fp32 = m->prod == SBFEM_PROD_FP32;
+  L.fp32 = m->prod != SBFEM_PROD_FP64;  // FP32 kernels also carry the 16-bit product forms
   L.force_only = force_only;
   L.threads8 = m->block_threads;
   L.threads_mixed = m->block_threads_mixed;
@@ -638,16 +698,20 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   auto H2D = [&](void* dst, const void* src, size_t bytes) {
     if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
   };
-  int64_t bytes = ndof * 8 * 4 + 256 * 8 + 64;
+  int64_t bytes = 0;
 #define ALLOC(ptr, n)                                            \
   if (e == hipSuccess) {                                         \
     e = dalloc(&m->ptr, (size_t)(n));                            \
     bytes += (int64_t)(n) * (int64_t)sizeof(*m->ptr);            \
   }
-  ALLOC(u, ndof)
-  ALLOC(um1, ndof)
+  // state storage u, u_prev (and M^-1: FP32 with FP32 state, else FP64)
+  const int64_t sbytes = state_bytes(d->state, ndof);
+  const int64_t mbytes = ndof * (d->state == SBFEM_STATE_FP32 ? 4 : 8);
+  if (e == hipSuccess) e = hipMalloc(&m->u, sbytes);
+  if (e == hipSuccess) e = hipMalloc(&m->um1, sbytes);
+  if (e == hipSuccess) e = hipMalloc(&m->minv, mbytes);
+  bytes += 2 * sbytes + mbytes;
   ALLOC(f, ndof)
-  ALLOC(minv, ndof)
   ALLOC(matE, 256)
   ALLOC(flag_d, 1)
 
@@ -693,7 +757,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     bool ok = false;
     // LDS per block: FP64 forces of the owned nodes, u of the local nodes (FP64: 24 B per node;
     // FP32: 12 B, 16 B in pure 8-node tiles)
-    const int64_t node_bytes = d->prod == SBFEM_PROD_FP32 ? 16 : 24;
+    const int64_t node_bytes = d->prod != SBFEM_PROD_FP64 ? 16 : 24;
     for (int32_t tn = tn0; tn >= 32; tn /= 2) {
       if (sbfem::build_owner_tiles(ti, tn, to) && node_bytes * to.max_local + 24 * to.tile_nodes <= lds_max) {
         m->lds_bytes = (int32_t)(node_bytes * to.max_local + 24 * to.tile_nodes);
@@ -754,6 +818,12 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
       for (int i = 0; i < WC; ++i) {
         ws64[WC * c + i] = se * p->Wc[i];
         ws32[WC * c + i] = (float)ws64[WC * c + i];
+      }
+      if (d->prod == SBFEM_PROD_FP16 || d->prod == SBFEM_PROD_BF16) {
+        // 16-bit operands: the unscaled coefficients rounded to 16 bits, s_e applied after
+        for (int i = 0; i < WC - 1; ++i)
+          ws32[WC * c + i] = d->prod == SBFEM_PROD_FP16 ? round_fp16((float)p->Wc[i]) : round_bf16((float)p->Wc[i]);
+        ws32[WC * c + WC - 1] = (float)se;
       }
     }
     ALLOC(dWs64, ws64.size())
@@ -866,7 +936,13 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   m->bytes = bytes;
   if (e == hipSuccess) e = hipHostMalloc((void**)&m->flag_h, sizeof(int32_t), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&m->flag_ev, hipEventDisableTiming);
-  H2D(m->minv, minv.data(), ndof * 8);
+  std::vector<float> minv32;
+  if (d->state == SBFEM_STATE_FP32) {
+    minv32.assign(minv.begin(), minv.end());
+    H2D(m->minv, minv32.data(), ndof * 4);
+  } else {
+    H2D(m->minv, minv.data(), ndof * 8);
+  }
   H2D(m->matE, matE.data(), 256 * 8);
   if (e == hipSuccess) e = hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s);
   if (e == hipSuccess) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
@@ -891,7 +967,8 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     if (d->v0) v0[i] = d->v0[ex];
     if (minv[i] == 0.0) u0[i] = v0[i] = 0.0;
   }
-  H2D(m->u, u0.data(), ndof * 8);
+  const std::vector<char> u0raw = pack_state(d->state, u0.data(), ndof);
+  H2D(m->u, u0raw.data(), u0raw.size());
   if (e == hipSuccess && d->u0) {
     sbfem_status fs = internal_force(m, s);
     if (fs != SBFEM_OK) {
@@ -910,13 +987,15 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     const double a0 = minv[i] * (fext[i] - ku0[i]) - (minv[i] != 0.0 ? d->alpha * v0[i] : 0.0);
     um1[i] = u0[i] - d->dt * v0[i] + 0.5 * d->dt * d->dt * a0;
   }
-  H2D(m->um1, um1.data(), ndof * 8);
+  const std::vector<char> um1raw = pack_state(d->state, um1.data(), ndof);
+  H2D(m->um1, um1raw.data(), um1raw.size());
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     sbfem_destroy_mesh(m);
     return fail(SBFEM_EDEVICE, "create_mesh initial state: %s", hipGetErrorString(e));
   }
   m->int2ext.swap(int2ext);
+  m->mdiag.swap(mdiag);
   *out = m;
   return SBFEM_OK;
 }
@@ -947,7 +1026,8 @@ static sbfem_status enqueue_step(sbfem_mesh* m, hipStream_t s) {
   sbfem_status st = internal_force(m, s);
   if (st != SBFEM_OK) return st;
   h(3, true, s);
-  HIP_TRY(sbfem::launch_update(m->u, m->um1, m->f, m->minv, m->ndof, m->dt * m->dt, 0.5 * m->alpha * m->dt, s));
+  HIP_TRY(sbfem::launch_update((const double*)m->u, (double*)m->um1, m->f, (const double*)m->minv, m->ndof,
+                               m->dt * m->dt, 0.5 * m->alpha * m->dt, s));
   h(3, false, s);
   std::swap(m->u, m->um1);
   m->step++;
@@ -955,7 +1035,10 @@ static sbfem_status enqueue_step(sbfem_mesh* m, hipStream_t s) {
 }
 
 static sbfem_status finish_steps(sbfem_mesh* m, hipStream_t s) {
-  HIP_TRY(sbfem::launch_finite(m->u, m->ndof, m->flag_d, s));
+  if (m->state_mode == SBFEM_STATE_FP64)
+    HIP_TRY(sbfem::launch_finite((const double*)m->u, m->ndof, m->flag_d, s));
+  else  // FP32 values, or the high parts of compensated pairs
+    HIP_TRY(sbfem::launch_finite32((const float*)m->u, m->ndof, m->flag_d, s));
   HIP_TRY(hipMemcpyAsync(m->flag_h, m->flag_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(m->flag_ev, s));
   m->flag_pending = true;
@@ -1102,19 +1185,24 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
 
 sbfem_status sbfem_read_state(sbfem_mesh* m, int32_t which, double* host_out, int64_t* step, void* hip_stream) {
   if (!m || !host_out) return fail(SBFEM_EINVAL, "null argument");
-  if (which < 0 || which > 2) return fail(SBFEM_EINVAL, "which must be 0, 1 or 2");
+  if (which < 0 || which > 3) return fail(SBFEM_EINVAL, "which must be 0, 1, 2 or 3");
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t s = (hipStream_t)hip_stream;
   std::vector<double> tmp(m->ndof);
-  if (which == 2) {
+  if (which == 3) {
+    tmp = m->mdiag;
+  } else if (which == 2) {
     sbfem_status st = internal_force(m, s);
     if (st != SBFEM_OK) return st;
     HIP_TRY(hipMemcpyAsync(tmp.data(), m->f, m->ndof * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(sbfem::launch_fill(m->f, m->ndof, 0.0, s));
+    HIP_TRY(hipStreamSynchronize(s));
   } else {
-    HIP_TRY(hipMemcpyAsync(tmp.data(), which == 0 ? m->u : m->um1, m->ndof * 8, hipMemcpyDeviceToHost, s));
+    std::vector<char> raw(state_bytes(m->state_mode, m->ndof));
+    HIP_TRY(hipMemcpyAsync(raw.data(), which == 0 ? m->u : m->um1, raw.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    unpack_state(m->state_mode, raw.data(), m->ndof, tmp.data());
   }
-  HIP_TRY(hipStreamSynchronize(s));
   for (int64_t i = 0; i < m->ndof; ++i) host_out[3 * (int64_t)m->int2ext[i / 3] + i % 3] = tmp[i];
   if (step) *step = m->step;
   return check_flag(m);
@@ -1132,8 +1220,10 @@ sbfem_status sbfem_write_state(sbfem_mesh* m, const double* u_n, const double* u
     a[i] = u_n[e];
     b[i] = u_nm1[e];
   }
-  HIP_TRY(hipMemcpyAsync(m->u, a.data(), m->ndof * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(m->um1, b.data(), m->ndof * 8, hipMemcpyHostToDevice, s));
+  const std::vector<char> ra = pack_state(m->state_mode, a.data(), m->ndof);
+  const std::vector<char> rb = pack_state(m->state_mode, b.data(), m->ndof);
+  HIP_TRY(hipMemcpyAsync(m->u, ra.data(), ra.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(m->um1, rb.data(), rb.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s));
   HIP_TRY(hipStreamSynchronize(s));
   m->step = step;

@@ -48,8 +48,11 @@ __device__ __forceinline__ T pick3t(int i, T x, T y, T z) {
 __device__ __forceinline__ constexpr int other_lo(int m) { return m == 0 ? 1 : 0; }
 __device__ __forceinline__ constexpr int other_hi(int m) { return m == 2 ? 1 : 2; }
 
+// With 16-bit products (rmode != 0, FP32 only) the transformed displacements are scaled by a
+// power of two and rounded to FP16 / BF16, the table holds the unscaled coefficients rounded
+// to 16 bits with s_e in C[31], and the products are scaled back by s_e / scale.
 template <typename T>
-__device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&fe)[24]) {
+__device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&fe)[24], int32_t rmode = 0) {
   T x[3][8];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -66,6 +69,22 @@ __device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&f
           if (b < 2 || k != 0) x[a][k] = lo + hi;  // the translation sum x[a][0] is never used
           x[a][k | (1 << b)] = hi - lo;
         }
+  T back = T(1);
+  if constexpr (sizeof(T) == 4) {
+    if (rmode) {
+      float mx = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 1; k < 8; ++k) mx = fmaxf(mx, fabsf(x[a][k]));
+      const float sx = pow2_scale(mx);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 1; k < 8; ++k) x[a][k] = round16(x[a][k] * sx, rmode);
+      back = C[31] / sx;
+    }
+  }
   T y[3][8];
 #pragma unroll
   for (int a = 0; a < 3; ++a) y[a][0] = T(0);
@@ -74,7 +93,11 @@ __device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&f
     const int t = 7 * h;
     const T dm = C[2 * h], o = C[2 * h + 1];
     const T x0 = x[0][t ^ 1], x1 = x[1][t ^ 2], x2 = x[2][t ^ 4];
-    const T os = o * (x0 + x1 + x2);
+    T sum = x0 + x1 + x2;
+    if constexpr (sizeof(T) == 4) {
+      if (rmode) sum = round16(sum, rmode);  // a product operand too
+    }
+    const T os = o * sum;
     y[0][t ^ 1] = fma(dm, x0, os);
     y[1][t ^ 2] = fma(dm, x1, os);
     y[2][t ^ 4] = fma(dm, x2, os);
@@ -96,6 +119,14 @@ __device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&f
       y[i][t ^ (1 << i)] = fma(B[1], xj, B[0] * xi);
       y[j][t ^ (1 << j)] = fma(B[3], xj, B[2] * xi);
       y[m][t ^ (1 << m)] = B[4] * x[m][t ^ (1 << m)];
+    }
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (rmode) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 1; k < 8; ++k) y[a][k] *= back;
     }
   }
 #pragma unroll
@@ -146,7 +177,7 @@ __device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, in
     }
   }
   T fe[24];
-  walsh8_sym<T>(as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64) + it.koff, ue, fe);
+  walsh8_sym<T>(as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64) + it.koff, ue, fe, FP32 ? a.round16 : 0);
   const uint32_t mask = it.mask;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -220,6 +251,18 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
       ue[3 * k + 2] = (T)s2 * pick3t<T>(p2, x, y, z);
     }
   }
+  double post = se;  // applied to each product row
+  if constexpr (FP32) {
+    if (a.round16) {  // 16-bit operands: scale by a power of two, round, undo the scale after
+      float mx = 0.0f;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) mx = fmaxf(mx, fabsf(ue[j]));
+      const float su = pow2_scale(mx);
+#pragma unroll
+      for (int j = 0; j < ND; ++j) ue[j] = round16(ue[j] * su, a.round16);
+      post = se / (double)su;
+    }
+  }
   cptr_t<T> Kp = as_const(FP32 ? (const T*)(a.K32 + it.koff) : (const T*)(a.K64 + it.koff));
 #pragma unroll
   for (int k = 0; k < NN; ++k) {
@@ -233,7 +276,7 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
       for (int j = 0; j < ND; ++j) acc = fma(Kp[i * ND + j], ue[j], acc);
       const int pc = c == 0 ? p0 : (c == 1 ? p1 : p2);
       const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
-      if (own) atomicAdd(fl + 3 * li[k] + pc, sc * se * (double)acc);
+      if (own) atomicAdd(fl + 3 * li[k] + pc, sc * post * (double)acc);
     }
   }
 }
@@ -259,14 +302,13 @@ __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile&
     for (int i = tid; i < n; i += nt) f[d0 + i] = fl[i];
     return;
   }
-  gptr_t<double> u = as_global(a.u);
-  gptr_t<double> minv = as_global(a.minv);
-  gmut_t<double> um1 = as_global_mut(a.um1);
   const double inv = 1.0 / (1.0 + a.c);
   for (int i = tid; i < n; i += nt) {
     const int64_t d = d0 + i;
-    const double un = FP32 ? u[d] : un_lds[i];
-    um1[d] = (a.dt2 * minv[d] * (-fl[i]) + 2.0 * un - (1.0 - a.c) * um1[d]) * inv;
+    const double un = FP32 ? state_load(a.u, a.state, a.ndof, d) : un_lds[i];
+    const double up = state_load(a.um1, a.state, a.ndof, d);
+    const double v = (a.dt2 * minv_load(a.minv, a.state, d) * (-fl[i]) + 2.0 * un - (1.0 - a.c) * up) * inv;
+    state_store(a.um1, a.state, a.ndof, d, v);
   }
 }
 
@@ -276,18 +318,20 @@ __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile&
 template <bool FP32>
 __device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& tile, typename LdsType<FP32>::T* ul,
                                            double* fl, int tid, int nt) {
-  gptr_t<double> u = as_global(a.u);
   gptr_t<int32_t> nodelist = as_global(a.nodelist);
   const int n_own = tile.n_own;
+  const int32_t sm = a.state;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
   if constexpr (FP32) {
-    r0 = u[3 * tile.own0 + 0];
-    r1 = u[3 * tile.own0 + 1];
-    r2 = u[3 * tile.own0 + 2];
+    r0 = state_load(a.u, sm, a.ndof, 3 * tile.own0 + 0);
+    r1 = state_load(a.u, sm, a.ndof, 3 * tile.own0 + 1);
+    r2 = state_load(a.u, sm, a.ndof, 3 * tile.own0 + 2);
   }
   for (int l = tid; l < tile.n_local; l += nt) {
     const int64_t g = l < n_own ? tile.own0 + l : (int64_t)nodelist[tile.node0 + l - n_own];
-    const double x = u[3 * g + 0], y = u[3 * g + 1], z = u[3 * g + 2];
+    const double x = state_load(a.u, sm, a.ndof, 3 * g + 0);
+    const double y = state_load(a.u, sm, a.ndof, 3 * g + 1);
+    const double z = state_load(a.u, sm, a.ndof, 3 * g + 2);
     if constexpr (FP32) {
       reinterpret_cast<float4*>(ul)[l] = make_float4((float)(x - r0), (float)(y - r1), (float)(z - r2), 0.0f);
     } else {
