@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsbfem.so")
 SOURCES = ["kernels.hip", "mixed_ebe_fp64.hip", "mixed_ebe_fp32.hip", "mixed_tiled_fp64.hip",
-           "mixed_tiled_fp32.hip", "sbfem.cpp", "tiling.cpp"]
+           "mixed_tiled_fp32.hip", "mixed_tiled_fp64r.hip", "mixed_tiled_fp32r.hip", "sbfem.cpp", "tiling.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -155,6 +155,7 @@ struct TiledLaunch {
   int64_t n_pure8 = 0, n_mixed = 0;
   int64_t k = 0;                       // batch: steps since the refs were recorded
   bool fp32 = false;
+  bool reduced = false;                // FP32 or compensated state, or 16-bit products
   bool force_only = false;
   int32_t threads8 = 512, threads_mixed = 256;
   size_t lds = 0;
@@ -168,6 +169,8 @@ void ebe_mixed_fp32_launch(const ElementArgs& a, const Tile* tiles, int64_t n, b
 void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_mixed_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_mixed_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_mixed_fp64r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_mixed_fp32r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 
 hipError_t launch_load(double* f, const int64_t* idx, const double* val, int64_t nnz, const LoadParams& L,
                        double t, hipStream_t s);

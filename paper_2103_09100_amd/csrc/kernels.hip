@@ -128,9 +128,9 @@ hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& h
     const TileWork* w = batch ? L.work_mixed : nullptr;
     const int64_t first = batch ? 0 : L.n_pure8;
     if (L.fp32)
-      tiled_mixed_fp32_launch(L, w, first, L.n_mixed, s);
+      (L.reduced ? tiled_mixed_fp32r_launch : tiled_mixed_fp32_launch)(L, w, first, L.n_mixed, s);
     else
-      tiled_mixed_fp64_launch(L, w, first, L.n_mixed, s);
+      (L.reduced ? tiled_mixed_fp64r_launch : tiled_mixed_fp64_launch)(L, w, first, L.n_mixed, s);
     hook(2, false, s);
   }
   return hipGetLastError();
@@ -152,18 +152,19 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 // pure 8-node owner tiles
 void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
-#define SBFEM_L(F)                                                                                              \
+#define SBFEM_L(F, R)                                                                                           \
   do {                                                                                                          \
     if (L.lds > 65536)                                                                                          \
-      (void)hipFuncSetAttribute((const void*)tiled_step8<F>, hipFuncAttributeMaxDynamicSharedMemorySize,         \
+      (void)hipFuncSetAttribute((const void*)tiled_step8<F, R>, hipFuncAttributeMaxDynamicSharedMemorySize,      \
                                 (int)L.lds);                                                                    \
-    hipLaunchKernelGGL((tiled_step8<F>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, L.refs,    \
+    hipLaunchKernelGGL((tiled_step8<F, R>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, L.refs, \
                        work, first, count, L.k, (int)L.force_only);                                             \
   } while (0)
-  if (L.fp32)
-    SBFEM_L(true);
-  else
-    SBFEM_L(false);
+  if (L.fp32) {
+    if (L.reduced) SBFEM_L(true, true); else SBFEM_L(true, false);
+  } else {
+    if (L.reduced) SBFEM_L(false, true); else SBFEM_L(false, false);
+  }
 #undef SBFEM_L
 }
 

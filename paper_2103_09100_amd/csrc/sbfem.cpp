@@ -557,6 +557,7 @@ static sbfem::TiledLaunch tiled_launch(const sbfem_mesh* m, bool force_only) {
   L.n_pure8 = m->n_pure8;
   L.n_mixed = m->n_mixed;
   L.fp32 = m->prod != SBFEM_PROD_FP64;  // FP32 kernels also carry the 16-bit product forms
+  L.reduced = m->state_mode != SBFEM_STATE_FP64 || m->prod == SBFEM_PROD_FP16 || m->prod == SBFEM_PROD_BF16;
   L.force_only = force_only;
   L.threads8 = m->block_threads;
   L.threads_mixed = m->block_threads_mixed;
@@ -1152,7 +1153,7 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
     std::vector<int64_t> st;
     for (int j = i; j < n; ++j)
       if (!used[j] && ms[j]->assembly == SBFEM_ASM_TILED && !ms[j]->profiling && ms[j]->P == ms[i]->P &&
-          ms[j]->prod == ms[i]->prod &&
+          ms[j]->prod == ms[i]->prod && ms[j]->state_mode == ms[i]->state_mode &&
           ms[j]->block_threads == ms[i]->block_threads &&
           ms[j]->block_threads_mixed == ms[i]->block_threads_mixed && n_steps[j] > 0) {
         g.push_back(ms[j]);

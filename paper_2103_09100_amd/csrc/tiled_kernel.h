@@ -155,7 +155,7 @@ struct LdsNode {
 
 // A regular 8-node cell of a kind-1 item: gather, structured Walsh product with the
 // class-scaled table, FP64 LDS atomics into the rows of owned corners.
-template <bool FP32>
+template <bool FP32, bool RED>
 __device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, int lane, int n_own,
                                       const typename LdsType<FP32>::T* __restrict__ ul, double* __restrict__ fl) {
   using T = typename LdsType<FP32>::T;
@@ -177,7 +177,7 @@ __device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, in
     }
   }
   T fe[24];
-  walsh8_sym<T>(as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64) + it.koff, ue, fe, FP32 ? a.round16 : 0);
+  walsh8_sym<T>(as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64) + it.koff, ue, fe, round_of<RED>(a));
   const uint32_t mask = it.mask;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -188,6 +188,18 @@ __device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, in
     atomicAdd(fp + 1, (double)fe[3 * c + 1]);
     atomicAdd(fp + 2, (double)fe[3 * c + 2]);
   }
+}
+
+// Precision forms: kernels instantiated with RED = false take FP64 state and no 16-bit
+// rounding as compile-time constants (the plain and mixed paths); RED = true reads them from
+// the argument block.
+template <bool RED>
+__device__ __forceinline__ int32_t state_of(const TiledArgs& a) {
+  return RED ? a.state : 0;
+}
+template <bool RED>
+__device__ __forceinline__ int32_t round_of(const TiledArgs& a) {
+  return RED ? a.round16 : 0;
 }
 
 // The block's tile: which mesh (single or batched launch), its argument block for
@@ -215,7 +227,7 @@ __device__ __forceinline__ bool block_tile(const MeshRef& single, const MeshRef*
 
 // Generic cell of NN nodes (any pattern): orientation per cell, dense master matrix,
 // scale s_e per cell.
-template <int NN, bool FP32>
+template <int NN, bool FP32, bool RED>
 __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it, int lane, int n_own,
                                           const typename LdsType<FP32>::T* __restrict__ ul,
                                           double* __restrict__ fl) {
@@ -253,13 +265,14 @@ __device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it
   }
   double post = se;  // applied to each product row
   if constexpr (FP32) {
-    if (a.round16) {  // 16-bit operands: scale by a power of two, round, undo the scale after
+    const int32_t rm = round_of<RED>(a);
+    if (rm) {  // 16-bit operands: scale by a power of two, round, undo the scale after
       float mx = 0.0f;
 #pragma unroll
       for (int j = 0; j < ND; ++j) mx = fmaxf(mx, fabsf(ue[j]));
       const float su = pow2_scale(mx);
 #pragma unroll
-      for (int j = 0; j < ND; ++j) ue[j] = round16(ue[j] * su, a.round16);
+      for (int j = 0; j < ND; ++j) ue[j] = round16(ue[j] * su, rm);
       post = se / (double)su;
     }
   }
@@ -292,7 +305,7 @@ __device__ __forceinline__ void tile_loads(const TiledArgs& a, const OwnerTile& 
 
 // Central-difference update of the owned dofs written over u_{n-1} (or R_int, force-only).
 // un_lds: u_n of the owned dofs as staged (FP64 staging holds u_n itself).
-template <bool FP32>
+template <bool FP32, bool RED>
 __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile& tile, const double* fl,
                                             const double* un_lds, int force_only, int tid, int nt) {
   const int64_t d0 = 3 * tile.own0;
@@ -305,22 +318,23 @@ __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile&
   const double inv = 1.0 / (1.0 + a.c);
   for (int i = tid; i < n; i += nt) {
     const int64_t d = d0 + i;
-    const double un = FP32 ? state_load(a.u, a.state, a.ndof, d) : un_lds[i];
-    const double up = state_load(a.um1, a.state, a.ndof, d);
-    const double v = (a.dt2 * minv_load(a.minv, a.state, d) * (-fl[i]) + 2.0 * un - (1.0 - a.c) * up) * inv;
-    state_store(a.um1, a.state, a.ndof, d, v);
+    const int32_t sm = state_of<RED>(a);
+    const double un = FP32 ? state_load(a.u, sm, a.ndof, d) : un_lds[i];
+    const double up = state_load(a.um1, sm, a.ndof, d);
+    const double v = (a.dt2 * minv_load(a.minv, sm, d) * (-fl[i]) + 2.0 * un - (1.0 - a.c) * up) * inv;
+    state_store(a.um1, sm, a.ndof, d, v);
   }
 }
 
 // Stage u_n of the tile's local nodes in LDS (owned nodes first, then the tile's node list)
 // and clear the owned forces.  FP32 products keep u minus the displacement of the tile's
 // first owned node, so that only variations across the tile are rounded.
-template <bool FP32>
+template <bool FP32, bool RED>
 __device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& tile, typename LdsType<FP32>::T* ul,
                                            double* fl, int tid, int nt) {
   gptr_t<int32_t> nodelist = as_global(a.nodelist);
   const int n_own = tile.n_own;
-  const int32_t sm = a.state;
+  const int32_t sm = state_of<RED>(a);
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
   if constexpr (FP32) {
     r0 = state_load(a.u, sm, a.ndof, 3 * tile.own0 + 0);
@@ -345,7 +359,7 @@ __device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& 
 
 // Tiles with cells of any pattern: kind-1 items take the 8-node path, the others the
 // dense product of their pattern.  LDS: the owned forces (FP64), then the staged u.
-template <bool FP32>
+template <bool FP32, bool RED>
 __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef* __restrict__ refs,
                                                   const TileWork* __restrict__ work, int64_t first, int64_t count,
                                                   int64_t k, int force_only) {
@@ -360,7 +374,7 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
   T* ul = (T*)(lds + 3 * (int64_t)n_own);
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  tile_stage<FP32>(a, tile, ul, fl, tid, nt);
+  tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
   // the wave index is uniform in a wave: say so, so item fields (and K_p) come through scalar loads
@@ -371,12 +385,12 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
     const CellItem it = load_const(items + w);
     if (lane >= it.count) continue;
     if (it.kind == 1) {
-      cell8<FP32>(a, it, lane, n_own, ul, fl);
+      cell8<FP32, RED>(a, it, lane, n_own, ul, fl);
       continue;
     }
 #define SBFEM_TCASE(N) \
   case N:              \
-    tile_cell<N, FP32>(a, it, lane, n_own, ul, fl); \
+    tile_cell<N, FP32, RED>(a, it, lane, n_own, ul, fl); \
     break;
     switch (it.nn) {
       SBFEM_TCASE(8) SBFEM_TCASE(9) SBFEM_TCASE(10) SBFEM_TCASE(11) SBFEM_TCASE(12) SBFEM_TCASE(13)
@@ -390,13 +404,13 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
   }
   __syncthreads();
   // FP64 staging keeps u_n of the owned nodes at the start of ul (owned nodes come first)
-  tile_update<FP32>(a, tile, fl, (const double*)ul, force_only, tid, nt);
+  tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
 }
 
 // Tiles whose cells are all regular 8-node cells in identity orientation (the master
 // matrix is invariant under the 48 cube transformations, so the set-up maps every such
 // cell onto it without a transformation): only kind-1 items.
-template <bool FP32>
+template <bool FP32, bool RED>
 __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
                                                    const TileWork* __restrict__ work, int64_t first,
                                                    int64_t count, int64_t k, int force_only) {
@@ -411,7 +425,7 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   T* ul = (T*)(lds + 3 * (int64_t)n_own);
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  tile_stage<FP32>(a, tile, ul, fl, tid, nt);
+  tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -420,10 +434,10 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   for (int w = wave; w < tile.n_items; w += n_waves) {
     const CellItem it = load_const(items + w);
     if (lane >= it.count) continue;
-    cell8<FP32>(a, it, lane, n_own, ul, fl);
+    cell8<FP32, RED>(a, it, lane, n_own, ul, fl);
   }
   __syncthreads();
-  tile_update<FP32>(a, tile, fl, (const double*)ul, force_only, tid, nt);
+  tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
 }
 
 }  // namespace sbfem

@@ -9,9 +9,9 @@
 //
 // Regular 8-node cells (pattern p8, identity orientation) form kind-1 items:
 // one scale class (level, material) per item so the pre-scaled Walsh table is
-// uniform in a wave, full waves (cells sorted by row mask and then in cell
-// order, the item's mask is the union), and the eight local node indices of a
-// cell stored together (16 bytes, lane-major).  Tiles with only such cells run
+// uniform in a wave, full waves of cells in cell (Morton) order (the item's
+// mask is the union of the cells' owned-corner masks), and the eight local node
+// indices of a cell stored together (16 bytes, lane-major).  Tiles with only such cells run
 // the dedicated 8-node kernel.
 #include <algorithm>
 #include <thread>
@@ -121,8 +121,8 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
       if (in.p8 < 0 || in.pattern[c] != in.p8) r.pure8 = false;
       recs.push_back({(int32_t)j, mask, (int32_t)in.pattern[c]});
     }
-    // regular 8-node cells (every cell of a pure tile): kind-1 items of one scale class, cells
-    // sorted by row mask and then in cell order, full waves with the union mask
+    // regular 8-node cells (every cell of a pure tile): kind-1 items of one scale class, full
+    // waves with the union of the cells' owned-corner masks
     std::vector<CellRec> r8, rg;
     for (const auto& rc : recs) {
       if (in.p8 >= 0 && in.pattern[cells[rc.c]] == in.p8)
@@ -133,7 +133,9 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
     auto by_key = [](const CellRec& a, const CellRec& b) {
       return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
     };
-    std::stable_sort(r8.begin(), r8.end(), by_key);
+    // regular cells: by scale class, then in cell (Morton) order, so that the lanes of a wave hold
+    // neighbouring cells and their corner nodes spread over the LDS banks
+    std::stable_sort(r8.begin(), r8.end(), [](const CellRec& a, const CellRec& b) { return a.pattern < b.pattern; });
     std::stable_sort(rg.begin(), rg.end(), by_key);
     // generic items: group by (pattern, row mask); small groups of one pattern share an item
     const size_t kMerge = 16;
