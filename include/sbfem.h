@@ -190,8 +190,9 @@ sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches);
  *  6 and 7 algorithmic bytes per step of the 8-node-tile kernel and of the
  *  other-tile kernel: 32 B per owned dof (u_n, u_{n-1}, M^-1 read, u_{n+1}
  *  written), 4 B per node id + 3 B per cell for the cells whose lowest node the
- *  kernel's tiles own, 16 B per load entry (eq. DnMdiag, Alg. 1 time loop).
- * Entries not available for the mesh's assembly are 0.
+ *  kernel's tiles own, 16 B per load entry (eq. DnMdiag, Alg. 1 time loop),
+ *  8 the largest number of local nodes of a tile, 9 the on-chip memory of a block
+ *  (bytes).  Entries not available for the mesh's assembly are 0.
  */
 sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals);
 

@@ -226,7 +226,7 @@ class Mesh:
         return dict(device_bytes=b.value, n_dof=n.value, n_colours=c.value)
 
     LAYOUT = ("tiles_8node", "tiles_other", "items", "local_nodes", "cell_entries", "tile_nodes",
-              "alg_bytes_8node", "alg_bytes_other")
+              "alg_bytes_8node", "alg_bytes_other", "max_local_nodes", "lds_bytes")
 
     def layout(self):
         v = np.zeros(len(self.LAYOUT), dtype=np.int64)

@@ -205,7 +205,7 @@ struct sbfem_mesh {
   int32_t block_threads = 512;        // 8-node owner tiles
   int32_t block_threads_mixed = 256;  // owner tiles with larger cells
   bool walsh = true;
-  int64_t layout[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t layout[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -799,6 +799,8 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
       m->layout[6] = b8;
       m->layout[7] = bo;
     }
+    m->layout[8] = to.max_local;
+    m->layout[9] = m->lds_bytes;
     ALLOC(otiles, to.tiles.size())
     ALLOC(items, to.items.size())
     ALLOC(lidx, to.lidx.size())
@@ -1259,7 +1261,7 @@ sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches) {
 
 sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals) {
   if (!m || (n_vals > 0 && !vals)) return fail(SBFEM_EINVAL, "null argument");
-  for (int i = 0; i < n_vals; ++i) vals[i] = i < 8 ? m->layout[i] : 0;
+  for (int i = 0; i < n_vals; ++i) vals[i] = i < 10 ? m->layout[i] : 0;
   return SBFEM_OK;
 }
 

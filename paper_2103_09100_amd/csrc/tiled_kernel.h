@@ -155,11 +155,15 @@ struct LdsNode {
 
 // A regular 8-node cell of a kind-1 item: gather, structured Walsh product with the
 // class-scaled table, FP64 LDS atomics into the rows of owned corners.
+// the lane's 16-byte record of local node indices in a kind-1 item
+__device__ __forceinline__ uint4 cell8_record(const TiledArgs& a, const CellItem& it, int lane) {
+  return load_global(as_global(reinterpret_cast<const uint4*>(a.lidx)) + ((it.lidx0 >> 3) + lane));
+}
+
 template <bool FP32, bool RED>
-__device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, int lane, int n_own,
+__device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, const uint4 q, int n_own,
                                       const typename LdsType<FP32>::T* __restrict__ ul, double* __restrict__ fl) {
   using T = typename LdsType<FP32>::T;
-  const uint4 q = load_global(as_global(reinterpret_cast<const uint4*>(a.lidx)) + ((it.lidx0 >> 3) + lane));
   const int li[8] = {(int)(q.x & 0xFFFFu), (int)(q.x >> 16), (int)(q.y & 0xFFFFu), (int)(q.y >> 16),
                      (int)(q.z & 0xFFFFu), (int)(q.z >> 16), (int)(q.w & 0xFFFFu), (int)(q.w >> 16)};
   T ue[24];
@@ -385,7 +389,7 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
     const CellItem it = load_const(items + w);
     if (lane >= it.count) continue;
     if (it.kind == 1) {
-      cell8<FP32, RED>(a, it, lane, n_own, ul, fl);
+      cell8<FP32, RED>(a, it, cell8_record(a, it, lane), n_own, ul, fl);
       continue;
     }
 #define SBFEM_TCASE(N) \
@@ -425,19 +429,71 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   T* ul = (T*)(lds + 3 * (int64_t)n_own);
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
-  __syncthreads();
-  if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int n_waves = nt >> 6;
   cptr_t<CellItem> items = as_const(a.items) + tile.item0;
-  for (int w = wave; w < tile.n_items; w += n_waves) {
-    const CellItem it = load_const(items + w);
-    if (lane >= it.count) continue;
-    cell8<FP32, RED>(a, it, lane, n_own, ul, fl);
+  // Loads whose addresses are known now are issued before the staging so that their latency
+  // overlaps it: the wave's first cell record and, with FP64 state, the update operands of
+  // the thread's owned dofs (at most 3 per thread).
+  constexpr int kPre = 3;
+  const int n_dof = 3 * n_own;
+  const bool pre = !RED && !force_only && n_dof <= kPre * nt;
+  double pu[kPre], pp[kPre], pm[kPre];
+  if (pre) {
+    const int64_t d0 = 3 * tile.own0;
+    const gptr_t<double> u = as_global((const double*)a.u), up = as_global((const double*)a.um1),
+                         mi = as_global((const double*)a.minv);
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) {
+      const int i = tid + j * nt;
+      pu[j] = pp[j] = pm[j] = 0.0;
+      if (i < n_dof) {
+        if constexpr (FP32) pu[j] = u[d0 + i];
+        pp[j] = up[d0 + i];
+        pm[j] = mi[d0 + i];
+      }
+    }
+  }
+  int w = wave;
+  CellItem it{};
+  uint4 q = make_uint4(0, 0, 0, 0);
+  if (w < tile.n_items) {
+    it = load_const(items + w);
+    if (lane < it.count) q = cell8_record(a, it, lane);
+  }
+  tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
+  __syncthreads();
+  if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
+  while (w < tile.n_items) {
+    // the next record is requested before this cell's work
+    const int wn = w + n_waves;
+    CellItem itn{};
+    uint4 qn = make_uint4(0, 0, 0, 0);
+    if (wn < tile.n_items) {
+      itn = load_const(items + wn);
+      if (lane < itn.count) qn = cell8_record(a, itn, lane);
+    }
+    if (lane < it.count) cell8<FP32, RED>(a, it, q, n_own, ul, fl);
+    w = wn;
+    it = itn;
+    q = qn;
   }
   __syncthreads();
-  tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
+  if (pre) {
+    const int64_t d0 = 3 * tile.own0;
+    const gmut_t<double> up = as_global_mut((double*)a.um1);
+    const double inv = 1.0 / (1.0 + a.c);
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) {
+      const int i = tid + j * nt;
+      if (i < n_dof) {
+        const double un = FP32 ? pu[j] : (double)ul[i];
+        up[d0 + i] = (a.dt2 * pm[j] * (-fl[i]) + 2.0 * un - (1.0 - a.c) * pp[j]) * inv;
+      }
+    }
+  } else {
+    tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
+  }
 }
 
 }  // namespace sbfem
