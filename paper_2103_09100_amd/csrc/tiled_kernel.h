@@ -364,9 +364,9 @@ __device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& 
 // Tiles with cells of any pattern: kind-1 items take the 8-node path, the others the
 // dense product of their pattern.  LDS: the owned forces (FP64), then the staged u.
 template <bool FP32, bool RED>
-__global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef* __restrict__ refs,
-                                                  const TileWork* __restrict__ work, int64_t first, int64_t count,
-                                                  int64_t k, int force_only) {
+__device__ __forceinline__ void tiled_step_body(MeshRef single, const MeshRef* __restrict__ refs,
+                                                const TileWork* __restrict__ work, int64_t first, int64_t count,
+                                                int64_t k, int force_only) {
   using T = typename LdsType<FP32>::T;
   extern __shared__ double lds[];
   TiledArgs a;
@@ -409,6 +409,16 @@ __global__ void __launch_bounds__(512) tiled_step(MeshRef single, const MeshRef*
   __syncthreads();
   // FP64 staging keeps u_n of the owned nodes at the start of ul (owned nodes come first)
   tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
+}
+
+// The kernel of the tiles with hanging-node cells.  FP32 products are held to 128 VGPRs
+// (4 waves per SIMD): the rare large dense cells spill a little, the regular cells of these
+// tiles gain occupancy.  FP64 products keep the register file (their spills cost more).
+template <bool FP32, bool RED>
+__global__ void __launch_bounds__(512, FP32 ? 4 : 1) tiled_step(MeshRef single, const MeshRef* __restrict__ refs,
+                                                                 const TileWork* __restrict__ work, int64_t first,
+                                                                 int64_t count, int64_t k, int force_only) {
+  tiled_step_body<FP32, RED>(single, refs, work, first, count, k, force_only);
 }
 
 // Tiles whose cells are all regular 8-node cells in identity orientation (the master
