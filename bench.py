@@ -429,7 +429,7 @@ def main():
         log(f"[bench] warning: per-kernel algorithmic bytes {lay['alg_bytes_8node'] + lay['alg_bytes_other']} "
             f"!= step bytes {ab['step']}")
     achieved = alg8 / (k8["ms_avg"] * 1e-3) / 1e9 if k8["ms_avg"] > 0 else 0.0
-    kname = "tiled_step8<true>" if head.startswith("fp32") else "tiled_step8<false>"
+    kname = "tiled_step8<true, false>" if head.startswith("fp32") else "tiled_step8<false, false>"
     traffic = counter_traffic(kname)
     out = {
         "metric": METRIC,
