@@ -196,6 +196,19 @@ sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches);
  */
 sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals);
 
+/*
+ * Device memory of objects created from now on (pattern libraries, meshes, and the work lists
+ * of sbfem_step_batch) comes from alloc(bytes, user) and goes back through release(ptr, user),
+ * e.g. a framework's caching allocator; both NULL restores hipMalloc/hipFree.  alloc must
+ * return device memory of the current device aligned to at least 256 bytes, or NULL (the
+ * creating call then fails with SBFEM_ENOMEM).  Each object keeps the pair it was created
+ * with and releases through it when destroyed, so the pair must stay callable until then.
+ * Process-wide setting, not synchronised with concurrent creation calls.
+ * Errors: SBFEM_EINVAL if exactly one of alloc, release is NULL.
+ */
+sbfem_status sbfem_set_allocator(void* (*alloc)(size_t bytes, void* user), void (*release)(void* ptr, void* user),
+                                 void* user);
+
 /* Last error message of the calling thread ("" if none). */
 const char* sbfem_last_error(void);
 

@@ -37,7 +37,8 @@ LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
 EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint",
            "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n",
            "sbfem_step_batch", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
-           "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_last_error"]
+           "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_set_allocator",
+           "sbfem_last_error"]
 KERNEL_CLASSES = ("load", "element_8node", "element_larger", "update")
 
 
@@ -75,6 +76,9 @@ _lib.sbfem_mesh_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
 _lib.sbfem_profile.argtypes = [_P, C.c_int32]
 _lib.sbfem_profile_read.argtypes = [_P, _P, _P]
 _lib.sbfem_mesh_layout.argtypes = [_P, _P, C.c_int32]
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_lib.sbfem_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, _P]
 _lib.sbfem_last_error.argtypes = []
 _lib.sbfem_last_error.restype = C.c_char_p
 for _name in EXPORTS:
@@ -258,3 +262,18 @@ def step_batch(meshes, steps, stream=None):
     arr = (_P * len(meshes))(*[m.handle for m in meshes])
     st = np.ascontiguousarray(steps, dtype=np.int64)
     _check(_lib.sbfem_step_batch(arr, len(meshes), st.ctypes.data, _stream(stream)))
+
+
+_ALLOCATOR_KEEP = []  # the C callbacks must outlive every object created with them
+
+
+def set_allocator(alloc=None, release=None):
+    """sbfem_set_allocator: alloc(nbytes) -> device address (int, 0 on failure) and
+    release(address); both None restores hipMalloc/hipFree."""
+    if alloc is None and release is None:
+        _check(_lib.sbfem_set_allocator(ALLOC_FN(), RELEASE_FN(), None))
+        return
+    fa = ALLOC_FN(lambda n, user: int(alloc(int(n))) or None)
+    fr = RELEASE_FN(lambda p, user: release(int(p)))
+    _ALLOCATOR_KEEP.append((fa, fr))
+    _check(_lib.sbfem_set_allocator(fa, fr, None))

@@ -45,16 +45,41 @@ sbfem_status fail(sbfem_status s, const char* fmt, ...) {
                   #call, hipGetErrorString(e_), __FILE__, __LINE__);                     \
   } while (0)
 
-template <class T>
-hipError_t dalloc(T** p, size_t n) {
+// Device memory: hipMalloc/hipFree, or the caller's allocator (sbfem_set_allocator).  Each
+// object keeps the allocator it was created with and returns its memory through it.
+struct Allocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* user = nullptr;
+};
+Allocator g_alloc;
+
+hipError_t dalloc_bytes(const Allocator& A, void** p, size_t bytes) {
   *p = nullptr;
-  if (n == 0) return hipSuccess;
-  return hipMalloc((void**)p, n * sizeof(T));
+  if (bytes == 0) return hipSuccess;
+  if (A.alloc) {
+    *p = A.alloc(bytes, A.user);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
 }
 
 template <class T>
-void dfree(T*& p) {
-  if (p) (void)hipFree((void*)p);
+hipError_t dalloc(const Allocator& A, T** p, size_t n) {
+  void* q = nullptr;
+  const hipError_t e = dalloc_bytes(A, &q, n * sizeof(T));
+  *p = (T*)q;
+  return e;
+}
+
+template <class T>
+void dfree(const Allocator& A, T*& p) {
+  if (p) {
+    if (A.release)
+      A.release((void*)p, A.user);
+    else
+      (void)hipFree((void*)p);
+  }
   p = nullptr;
 }
 
@@ -136,6 +161,7 @@ double load_time_host(const sbfem::LoadParams& L, double t) {
 }  // namespace
 
 struct sbfem_patterns {
+  Allocator alloc;
   int32_t n = 0;
   int device = 0;
   std::vector<int32_t> ndof;
@@ -155,6 +181,7 @@ struct sbfem_patterns {
 };
 
 struct sbfem_mesh {
+  Allocator alloc;
   const sbfem_patterns* P = nullptr;
   int device = 0;
   int64_t N = 0, C = 0, ndof = 0;
@@ -264,6 +291,15 @@ extern "C" {
 
 const char* sbfem_last_error(void) { return g_err.c_str(); }
 
+sbfem_status sbfem_set_allocator(void* (*alloc)(size_t bytes, void* user), void (*release)(void* ptr, void* user),
+                                 void* user) {
+  if ((alloc == nullptr) != (release == nullptr)) return fail(SBFEM_EINVAL, "give both alloc and release, or neither");
+  g_alloc.alloc = alloc;
+  g_alloc.release = release;
+  g_alloc.user = user;
+  return SBFEM_OK;
+}
+
 sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, const int32_t* ndof,
                                    const double* K, const double* m, const double* omega, void* hip_stream) {
   if (!out) return fail(SBFEM_EINVAL, "null output handle");
@@ -271,6 +307,7 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
   if (n_patterns <= 0 || n_patterns > 65535 || !ndof || !K || !m || !omega)
     return fail(SBFEM_EINVAL, "bad pattern library arguments");
   auto* p = new sbfem_patterns();
+  p->alloc = g_alloc;
   p->n = n_patterns;
   int64_t ko = 0, mo = 0;
   for (int i = 0; i < n_patterns; ++i) {
@@ -382,10 +419,10 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
   }
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t e = hipGetDevice(&p->device);
-  if (e == hipSuccess) e = dalloc(&p->dK64, ko);
-  if (e == hipSuccess) e = dalloc(&p->dK32, ko);
-  if (e == hipSuccess) e = dalloc(&p->dK16, ko);
-  if (e == hipSuccess) e = dalloc(&p->dKb16, ko);
+  if (e == hipSuccess) e = dalloc(p->alloc, &p->dK64, ko);
+  if (e == hipSuccess) e = dalloc(p->alloc, &p->dK32, ko);
+  if (e == hipSuccess) e = dalloc(p->alloc, &p->dK16, ko);
+  if (e == hipSuccess) e = dalloc(p->alloc, &p->dKb16, ko);
   std::vector<float> K16(ko), Kb16(ko);
   for (int64_t i = 0; i < ko; ++i) {
     K16[i] = round_fp16(K32[i]);
@@ -397,10 +434,10 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
   if (e == hipSuccess) e = hipMemcpyAsync(p->dKb16, Kb16.data(), ko * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    dfree(p->dK64);
-    dfree(p->dK32);
-    dfree(p->dK16);
-    dfree(p->dKb16);
+    dfree(p->alloc, p->dK64);
+    dfree(p->alloc, p->dK32);
+    dfree(p->alloc, p->dK16);
+    dfree(p->alloc, p->dKb16);
     delete p;
     return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "pattern upload: %s", hipGetErrorString(e));
   }
@@ -411,10 +448,10 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
 void sbfem_destroy_patterns(sbfem_patterns* p) {
   if (!p) return;
   (void)hipSetDevice(p->device);
-  dfree(p->dK64);
-  dfree(p->dK32);
-  dfree(p->dK16);
-  dfree(p->dKb16);
+  dfree(p->alloc, p->dK64);
+  dfree(p->alloc, p->dK32);
+  dfree(p->alloc, p->dK16);
+  dfree(p->alloc, p->dKb16);
   delete p;
 }
 
@@ -452,27 +489,27 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   for (auto e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->flag_ev) (void)hipEventDestroy(m->flag_ev);
   if (m->flag_h) (void)hipHostFree(m->flag_h);
-  dfree(m->u);
-  dfree(m->um1);
-  dfree(m->f);
-  dfree(m->minv);
-  dfree(m->matE);
-  dfree(m->conn);
-  dfree(m->orient);
-  dfree(m->level);
-  dfree(m->material);
-  dfree(m->tiles);
-  dfree(m->load_idx);
-  dfree(m->load_val);
-  dfree(m->flag_d);
-  dfree(m->otiles);
-  dfree(m->items);
-  dfree(m->lidx);
-  dfree(m->nodelist);
-  dfree(m->tloads);
-  dfree(m->d_args);
-  dfree(m->dWs64);
-  dfree(m->dWs32);
+  dfree(m->alloc, m->u);
+  dfree(m->alloc, m->um1);
+  dfree(m->alloc, m->f);
+  dfree(m->alloc, m->minv);
+  dfree(m->alloc, m->matE);
+  dfree(m->alloc, m->conn);
+  dfree(m->alloc, m->orient);
+  dfree(m->alloc, m->level);
+  dfree(m->alloc, m->material);
+  dfree(m->alloc, m->tiles);
+  dfree(m->alloc, m->load_idx);
+  dfree(m->alloc, m->load_val);
+  dfree(m->alloc, m->flag_d);
+  dfree(m->alloc, m->otiles);
+  dfree(m->alloc, m->items);
+  dfree(m->alloc, m->lidx);
+  dfree(m->alloc, m->nodelist);
+  dfree(m->alloc, m->tloads);
+  dfree(m->alloc, m->d_args);
+  dfree(m->alloc, m->dWs64);
+  dfree(m->alloc, m->dWs32);
   delete m;
 }
 
@@ -630,6 +667,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   }
 
   auto* m = new sbfem_mesh();
+  m->alloc = g_alloc;
   m->P = p;
   (void)hipGetDevice(&m->device);
   m->N = N;
@@ -702,15 +740,15 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   int64_t bytes = 0;
 #define ALLOC(ptr, n)                                            \
   if (e == hipSuccess) {                                         \
-    e = dalloc(&m->ptr, (size_t)(n));                            \
+    e = dalloc(m->alloc, &m->ptr, (size_t)(n));                            \
     bytes += (int64_t)(n) * (int64_t)sizeof(*m->ptr);            \
   }
   // state storage u, u_prev (and M^-1: FP32 with FP32 state, else FP64)
   const int64_t sbytes = state_bytes(d->state, ndof);
   const int64_t mbytes = ndof * (d->state == SBFEM_STATE_FP32 ? 4 : 8);
-  if (e == hipSuccess) e = hipMalloc(&m->u, sbytes);
-  if (e == hipSuccess) e = hipMalloc(&m->um1, sbytes);
-  if (e == hipSuccess) e = hipMalloc(&m->minv, mbytes);
+  if (e == hipSuccess) e = dalloc_bytes(m->alloc, &m->u, sbytes);
+  if (e == hipSuccess) e = dalloc_bytes(m->alloc, &m->um1, sbytes);
+  if (e == hipSuccess) e = dalloc_bytes(m->alloc, &m->minv, mbytes);
   bytes += 2 * sbytes + mbytes;
   ALLOC(f, ndof)
   ALLOC(matE, 256)
@@ -1084,9 +1122,10 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
   }
   sbfem::MeshRef* d_refs = nullptr;
   sbfem::TileWork *d_w8 = nullptr, *d_wm = nullptr;
-  HIP_TRY(hipMalloc((void**)&d_refs, n * sizeof(sbfem::MeshRef)));
-  hipError_t e = hipMalloc((void**)&d_w8, std::max<int64_t>(1, tot8) * sizeof(sbfem::TileWork));
-  if (e == hipSuccess) e = hipMalloc((void**)&d_wm, std::max<int64_t>(1, totm) * sizeof(sbfem::TileWork));
+  const Allocator& A = g[0]->alloc;
+  HIP_TRY(dalloc(A, &d_refs, n));
+  hipError_t e = dalloc(A, &d_w8, (size_t)std::max<int64_t>(1, tot8));
+  if (e == hipSuccess) e = dalloc(A, &d_wm, (size_t)std::max<int64_t>(1, totm));
   if (e == hipSuccess) e = hipMemcpyAsync(d_refs, refs.data(), n * sizeof(sbfem::MeshRef), hipMemcpyHostToDevice, s);
   std::vector<sbfem::TileWork> w8, wm;
   std::vector<size_t> done(n, 0);
@@ -1124,9 +1163,9 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
     if (e == hipSuccess) e = sbfem::launch_tiled(L, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(d_refs);
-  (void)hipFree(d_w8);
-  (void)hipFree(d_wm);
+  dfree(A, d_refs);
+  dfree(A, d_w8);
+  dfree(A, d_wm);
   if (e != hipSuccess) return fail(SBFEM_EDEVICE, "batched step: %s", hipGetErrorString(e));
   for (size_t i = 0; i < n; ++i) {
     if (steps[i] & 1) std::swap(g[i]->u, g[i]->um1);

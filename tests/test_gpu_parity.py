@@ -265,3 +265,28 @@ def test_serving_results_equal_alone(sim_mod):
     stats = latency_stats(reqs)
     _say(f"[serve] {stats}")
     assert stats["n"] == len(reqs)
+
+
+def test_torch_caching_allocator_supplies_device_memory(sim_mod):
+    """sbfem_set_allocator: the same run with device memory from torch's caching allocator."""
+    import torch
+    from paper_2103_09100_amd.torch_memory import use_hip_allocator, use_torch_allocator
+    m = configs.small_zoo()
+    a = sim_mod.Simulation(m, prod="fp32")
+    a.step(60)
+    ref = a.u()
+    a.close()
+    before = torch.cuda.memory_allocated()
+    use_torch_allocator()
+    try:
+        b = sim_mod.Simulation(m, prod="fp32")
+        grown = torch.cuda.memory_allocated() - before
+        b.step(60)
+        got = b.u()
+        b.close()
+    finally:
+        use_hip_allocator()
+    _say(f"[torch allocator] {grown / 1e6:.1f} MB from torch, footprint {b.footprint / 1e6:.1f} MB")
+    assert grown >= 0.5 * b.footprint
+    assert torch.cuda.memory_allocated() == before
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()

@@ -69,3 +69,11 @@ def test_one_hip_runtime_per_process():
                              capture_output=True, text=True, timeout=300)
         assert out.returncode == 0, out.stderr
         assert out.stdout.split()[-1] == "1", (first, second, out.stdout)
+
+
+def test_allocator_hook_validation_without_device(binding):
+    lib = binding._lib
+    st = lib.sbfem_set_allocator(binding.ALLOC_FN(lambda n, u: None), binding.RELEASE_FN(), None)
+    assert st == binding.EINVAL and "both" in binding.last_error()
+    binding.set_allocator(lambda n: 0, lambda p: None)  # accepted; nothing allocated here
+    binding.set_allocator(None, None)
