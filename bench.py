@@ -180,27 +180,36 @@ def time_mode(sim, torch, stream, steps, warmup):
     return a.elapsed_time(b) / steps, kernels
 
 
-def cpu_baseline(seconds=12.0):
-    """The oracle (as it stands) on a bounded sample of the same recipe at levels 5/6."""
-    from threadpoolctl import threadpool_info
+def cpu_baseline(seconds=12.0, single_seconds=8.0):
+    """The oracle (as it stands) on a bounded sample of the same recipe at levels 5/6: its step
+    loop with the host's BLAS threads, and again limited to one core."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from meshgen import configs
     from oracle.solver import Oracle
     m = configs.inclusion_mesh(seed=0, lcoarse=5, lfine=6)
     configs._run_params(m, fm=4.0, n_steps=200)
     o = Oracle(m, workers=min(16, os.cpu_count() or 1))
     dt = 0.5 * o.critical_dt()
-    u, um1 = o.initial_state(dt)
-    t0 = time.perf_counter()
-    n = 0
-    while n < 3 or time.perf_counter() - t0 < seconds:
-        unew, _ = o.step(u, um1, n, dt)
-        um1, u = u, unew
-        n += 1
-    el = time.perf_counter() - t0
+
+    def loop(limit):
+        u, um1 = o.initial_state(dt)
+        t0 = time.perf_counter()
+        n = 0
+        while n < 3 or time.perf_counter() - t0 < limit:
+            unew, _ = o.step(u, um1, n, dt)
+            um1, u = u, unew
+            n += 1
+        return n, time.perf_counter() - t0
+
+    n, el = loop(seconds)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    with threadpool_limits(1):
+        n1, el1 = loop(single_seconds)
     return dict(value=m.n_dof * n / el, unit="DOF-steps/s", cores=int(threads), kind="oracle",
                 sample=f"oracle step loop, same recipe at octree levels 5/6 ({m.n_dof} dofs, {m.n_cells} cells), "
-                       f"{n} steps in {el:.1f} s")
+                       f"{n} steps in {el:.1f} s",
+                single_core=dict(value=m.n_dof * n1 / el1, unit="DOF-steps/s", cores=1,
+                                 sample=f"the same loop with one BLAS thread, {n1} steps in {el1:.1f} s"))
 
 
 def serving(torch, args):
@@ -228,13 +237,21 @@ def serving(torch, args):
         f"arrivals over {reqs[-1].arrival:.1f} s")
     device_patterns(reqs[0].mesh.nu)
     st, st2 = torch.cuda.Stream(), torch.cuda.Stream()
+    # owner-tile shapes tuned per size bucket before the clock starts (first request of each bucket)
+    from paper_2103_09100_amd.autotune import SERVING_CANDIDATES, ShapeCache
+    shapes = ShapeCache(prod=args.serve_prod, candidates=SERVING_CANDIDATES, stream=st.cuda_stream)
+    t0 = time.time()
+    for r in reqs:
+        shapes.shape(r.mesh)
+    log(f"[serve] tile shapes tuned for {len(shapes.shapes)} size buckets in {time.time() - t0:.0f} s: "
+        + ", ".join(f"4^{b}: {shapes.shapes[b][0]}" for b in sorted(shapes.shapes)))
     free = torch.cuda.mem_get_info()[0]
     out = {}
     for label, budget in (("budget", int(args.serve_budget_gb * 1e9)), ("full_hbm", int(0.9 * free))):
         for r in reqs:
             r.reset()
         srv = Server(budget_bytes=budget, quantum=args.serve_quantum, prod=args.serve_prod,
-                     stream=st.cuda_stream, setup_stream=st2.cuda_stream)
+                     stream=st.cuda_stream, setup_stream=st2.cuda_stream, shapes=shapes)
         t1 = time.time()
         srv.run(reqs)
         stats = latency_stats(reqs)
@@ -249,11 +266,16 @@ def serving(torch, args):
     worst = 0.0
     for i in pick:
         r = reqs[i]
-        sim = Simulation(r.mesh, prod=args.serve_prod, stream=st.cuda_stream)
+        tn, bt, btm = shapes.shape(r.mesh)
+        sim = Simulation(r.mesh, prod=args.serve_prod, stream=st.cuda_stream, tile_nodes=tn, block_threads=bt,
+                         block_threads_mixed=btm)
         sim.step(r.n_steps)
         alone = sim.u()
         sim.close()
         worst = max(worst, float(np.abs(r.result - alone).max() / max(np.abs(alone).max(), 1e-300)))
+    out["tile_shapes"] = {f"4^{b}": dict(chosen=list(shapes.shapes[b]),
+                                         ms_per_step={str(list(c)): round(ms, 4) for c, ms in shapes.tables[b]})
+                          for b in sorted(shapes.shapes)}
     out.update(requests=len(reqs), product=args.serve_prod, state="fp64", quantum=args.serve_quantum,
                dof_steps=float(total), alone_vs_served_max_rel=worst, alone_checked=[int(i) for i in pick],
                workload="Poisson stream (20/s) of seeded inclusion octrees, 1e4-5e6 dofs log-uniform, "

@@ -52,10 +52,11 @@ class Server:
     own stream so it overlaps the stepping of the admitted simulations."""
 
     def __init__(self, budget_bytes=4 << 30, quantum=50, prod="fp32", stream=None, setup_stream=None,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, shapes=None):
         self.budget = int(budget_bytes)
         self.quantum = int(quantum)
         self.prod = prod
+        self.shapes = shapes      # owner-tile shape per mesh: an object with .shape(mesh) (autotune.ShapeCache)
         self.stream = stream
         self.setup_stream = setup_stream
         self.clock = clock
@@ -63,7 +64,9 @@ class Server:
     def _prepare(self, req):
         pats = device_patterns(req.mesh.nu, self.setup_stream)
         pid, code, conn = req.canon if req.canon is not None else canonicalise(req.mesh)
-        desc, keep = binding.make_desc(req.mesh, pid, code, conn, dt=1.0, prod=self.prod, assembly="tiled")
+        tn, bt, btm = self.shapes.shape(req.mesh) if self.shapes is not None else (0, 0, 0)
+        desc, keep = binding.make_desc(req.mesh, pid, code, conn, dt=1.0, prod=self.prod, assembly="tiled",
+                                       tile_nodes=tn, block_threads=bt, block_threads_mixed=btm)
         dt_cr = binding.critical_dt(pats, desc)
         desc.dt = req.mesh.load.get("dt_factor", 0.5) * dt_cr
         return pats, desc, keep, binding.footprint(pats, desc)

@@ -290,3 +290,18 @@ def test_torch_caching_allocator_supplies_device_memory(sim_mod):
     assert grown >= 0.5 * b.footprint
     assert torch.cuda.memory_allocated() == before
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_autotuned_shape_gives_the_same_result(sim_mod):
+    from paper_2103_09100_amd.autotune import CANDIDATES, ShapeCache
+    m = configs.cfg2(lcoarse=2, lfine=5, delta=0.1)
+    cache = ShapeCache(prod="fp64", steps=4)
+    best = cache.shape(m)
+    _say(f"[autotune {m.n_dof} dofs] chosen {best}, table {cache.tables[cache.bucket(m)]}")
+    assert best in CANDIDATES and cache.shape(m) is best
+    ref = sim_mod.Simulation(m, prod="fp64")
+    ref.step(50)
+    tn, bt, btm = best
+    s = sim_mod.Simulation(m, prod="fp64", tile_nodes=tn, block_threads=bt, block_threads_mixed=btm)
+    s.step(50)
+    assert np.abs(s.u() - ref.u()).max() <= 1e-12 * np.abs(ref.u()).max()
