@@ -469,7 +469,7 @@ def main():
         "config": {"workload": f"{args.config}: {desc}", "n_dof": mesh.n_dof, "n_cells": mesh.n_cells,
                    "product": head.split(":")[0], "state": "fp64", "assembly": head.split(":")[1],
                    "steps_per_call": args.steps},
-        "roofline": {"bound": "hbm", "kernel": f"{kname}: owner tiles of 8-node cells (element forces + update)",
+        "roofline": {"bound": "hbm", "kernel": f"{kname}: owner-tile pass (regular 8-node cells, hanging-cell row forces, update)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "step_achieved": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9,

@@ -96,8 +96,9 @@ typedef struct {
   const double* v0;             /* host [3N] initial velocity, NULL = zero */
   /* owner-tile shape (TILED assembly); 0 = library default.  tile_nodes: nodes owned by one
      block (halved automatically until the block's on-chip memory fits); block_threads:
-     threads per block for tiles of 8-node cells, block_threads_mixed for the others
-     (multiples of 64, at most 512). */
+     threads per block of the owner-tile pass (regular 8-node cells and the update),
+     block_threads_mixed per block of the hanging-node cell pass (one wave per item of up
+     to 64 cells of one pattern); multiples of 64, at most 512. */
   int32_t tile_nodes;
   int32_t block_threads;
   int32_t block_threads_mixed;
@@ -175,8 +176,9 @@ sbfem_status sbfem_mesh_info(const sbfem_mesh* m, int64_t* device_bytes, int64_t
  * of step_n / step_batch on this mesh is bracketed by HIP events recorded on
  * the launch stream.  profile_read waits for the recorded work, returns the
  * summed milliseconds and launch counts per kernel class, and clears them.
- * Classes: 0 load, 1 element kernel of 8-node cells, 2 element kernel of
- * larger cells, 3 central-difference update.
+ * Classes: 0 load, 1 element kernel of 8-node cells (TILED: the owner-tile pass,
+ * which also applies the update), 2 element kernel of larger cells (TILED: the
+ * hanging-node cell pass), 3 central-difference update.
  */
 #define SBFEM_N_KERNEL_CLASSES 4
 sbfem_status sbfem_profile(sbfem_mesh* m, int32_t enable);
@@ -184,15 +186,16 @@ sbfem_status sbfem_profile_read(sbfem_mesh* m, double* ms, int64_t* launches);
 
 /*
  * Layout statistics (diagnostics): vals[0..n_vals) receives, in order,
- *  0 owner tiles with 8-node cells only, 1 other owner tiles, 2 cell items,
- *  3 local node entries over all tiles, 4 cell entries over all tiles (cells
- *  touching several tiles count once per tile), 5 nodes owned per tile,
- *  6 and 7 algorithmic bytes per step of the 8-node-tile kernel and of the
- *  other-tile kernel: 32 B per owned dof (u_n, u_{n-1}, M^-1 read, u_{n+1}
- *  written), 4 B per node id + 3 B per cell for the cells whose lowest node the
- *  kernel's tiles own, 16 B per load entry (eq. DnMdiag, Alg. 1 time loop),
- *  8 the largest number of local nodes of a tile, 9 the on-chip memory of a block
- *  (bytes).  Entries not available for the mesh's assembly are 0.
+ *  0 owner tiles that own no node of a hanging-node cell, 1 the other owner
+ *  tiles, 2 cell items of regular 8-node cells, 3 local node entries over all
+ *  tiles, 4 cell entries (regular cells once per tile they touch, plus the
+ *  hanging-node cells once each), 5 nodes owned per tile, 6 and 7 algorithmic
+ *  bytes per step of the owner-tile pass and of the hanging-node cell pass:
+ *  32 B per dof (u_n, u_{n-1}, M^-1 read, u_{n+1} written) and 16 B per load
+ *  entry in the owner-tile pass (eq. DnMdiag, Alg. 1 time loop), 4 B per node id
+ *  + 3 B per cell in the pass that computes the cell, 8 the largest number of
+ *  local nodes of a tile, 9 the on-chip memory of an owner-tile block (bytes).
+ *  Entries not available for the mesh's assembly are 0.
  */
 sbfem_status sbfem_mesh_layout(const sbfem_mesh* m, int64_t* vals, int32_t n_vals);
 

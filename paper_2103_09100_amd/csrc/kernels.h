@@ -18,33 +18,51 @@ struct LoadParams {
 
 // Owner tile: a block updates the nodes [own0, own0 + n_own) (internal ids).
 // Its local nodes are the owned ones (local i < n_own is node own0 + i) followed
-// by the other nodes its cells touch (local i >= n_own is nodelist[node0 + i - n_own]);
-// u of all of them is staged in LDS.
+// by the other nodes its regular cells touch (local i >= n_own is
+// nodelist[node0 + i - n_own]); u of all of them is staged in LDS.  The forces of
+// hanging-node cells on its owned dofs arrive as n_hpair (owned dof, result)
+// pairs at hpairs[hpair0...] into the hanging-cell pass's results.
 struct OwnerTile {
   int64_t node0;
   int64_t own0;
   int64_t item0;
+  int64_t hpair0;
   int32_t n_own;
   int32_t n_local;
   int32_t n_items;
   int32_t load0;
   int32_t n_load;
-  int32_t pad;
+  int32_t n_hpair;
 };
 
-// Up to one wave of cells of one pattern; rows (master slots) in mask are accumulated.
-// kind 0 (any pattern): node indices slot-major, lidx[lidx0 + k*count + lane], per-cell
-// orientation/level/material at cell0, koff = master matrix offset.
-// kind 1 (regular 8-node cells of one scale class, identity orientation): indices
-// lane-major, lidx[lidx0 + 8*lane + k] (lidx0 a multiple of 8), koff = kWalshC * class.
-struct CellItem {
-  int64_t lidx0;
+// A force of a hanging-node cell on an owned dof of a tile: hres[res] added to local dof ldof.
+struct HangPair {
+  int32_t ldof;
+  uint32_t res;
+};
+
+// Hanging-node cells (every cell that is not a regular 8-node cell), each once, in items of
+// up to a wave of cells of one pattern: cell i of the item is hanging cell cell0 + i, its
+// node k is hconn[conn0 + k * count + i] (internal ids); the force of its master row r
+// (oriented, scaled) goes to hres[res0 + r * 64 + i].
+struct HangItem {
   int64_t cell0;
-  int64_t koff;
+  int64_t conn0;
+  int64_t koff;     // master matrix offset
+  int64_t res0;
   int32_t nn;
   int32_t count;
+};
+
+// Up to one wave of regular 8-node cells of one scale class (identity orientation) in an owner
+// tile; rows of owned corners are accumulated (mask: union of the cells' owned corners).
+// Local node indices lane-major, lidx[lidx0 + 8*lane + k] (lidx0 a multiple of 8),
+// koff = kWalshC * scale class.
+struct CellItem {
+  int64_t lidx0;
+  int64_t koff;
+  int32_t count;
   uint32_t mask;
-  int32_t kind;
 };
 
 // Entries per scale class of the structured Walsh table of the 8-node cell (31 used).
@@ -61,9 +79,6 @@ struct TiledArgs {
   int64_t n_tiles;
   const CellItem* items;
   const uint16_t* lidx;
-  const uint8_t* orient;
-  const uint8_t* level;
-  const uint8_t* material;
   const int32_t* nodelist;
   const LoadEntry* loads;
   const double* matE;
@@ -76,6 +91,13 @@ struct TiledArgs {
   void* um1;            // u_{n-1} in, u_{n+1} out (owned nodes)
   const void* minv;     // FP64, or FP32 with FP32 state
   double* f;            // force-only mode: R_int of owned dofs written here
+  const HangItem* hitems;      // hanging-cell pass
+  const int32_t* hconn;
+  const uint8_t* horient;
+  const uint8_t* hlevel;
+  const uint8_t* hmaterial;
+  const HangPair* hpairs;      // per tile, its (owned dof, result) pairs
+  double* hres;                // forces of the hanging cells' rows, rewritten every step
   int64_t ndof;         // dofs of the mesh (offset of the low parts of compensated state)
   int32_t state;        // 0 FP64, 1 FP32, 2 compensated FP32 pair (hi at u[i], lo at u[ndof + i])
   int32_t round16;      // 16-bit product operands: 0 none, 1 FP16 (per-cell power-of-two scale), 2 BF16
@@ -84,8 +106,8 @@ struct TiledArgs {
   double dt2;
   double c;             // alpha dt / 2
   int32_t lds_bytes;    // dynamic LDS: 3 FP64 forces per owned node + 3 u values per local node
-  int32_t block_threads;        // 8-node tiles: 64..512, multiple of 64
-  int32_t block_threads_mixed;  // other tiles
+  int32_t block_threads;        // owner-tile pass: 64..512, multiple of 64
+  int32_t block_threads_mixed;  // hanging-cell pass (one wave per item)
 };
 
 // A block's work: up to kTile consecutive cells of one pattern segment.
@@ -145,20 +167,22 @@ struct TileWork {
   int64_t tile;
 };
 
-// Launch description: either one mesh (single, work == nullptr; tiles [0, n_pure8) of
-// 8-node cells only, then n_mixed others) or a batch (refs + work lists).
+// Launch description: either one mesh (single, work == nullptr) or a batch (refs + work
+// lists).  A step is two passes: the hanging-node cells (items [0, n_hang)), then every
+// owner tile (tiles [0, n_tiles)).  In a batch, TileWork::tile is the item or tile index.
 struct TiledLaunch {
   MeshRef single;
   const MeshRef* refs = nullptr;
-  const TileWork* work8 = nullptr;     // batch: 8-node-only tiles of every mesh
-  const TileWork* work_mixed = nullptr;
-  int64_t n_pure8 = 0, n_mixed = 0;
+  const TileWork* work8 = nullptr;     // batch: every owner tile of every mesh
+  const TileWork* work_hang = nullptr; // batch: every hanging-cell item of every mesh
+  int64_t n_tiles = 0, n_hang = 0;
   int64_t k = 0;                       // batch: steps since the refs were recorded
   bool fp32 = false;
   bool reduced = false;                // FP32 or compensated state, or 16-bit products
   bool force_only = false;
   int32_t threads8 = 512, threads_mixed = 256;
-  size_t lds = 0;
+  size_t lds = 0;                      // owner-tile pass
+  size_t lds_hang = 0;                 // hanging-cell pass
 };
 
 hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& hook = LaunchHook());
@@ -167,10 +191,10 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 void ebe_mixed_fp64_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
 void ebe_mixed_fp32_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
 void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
-void tiled_mixed_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
-void tiled_mixed_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
-void tiled_mixed_fp64r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
-void tiled_mixed_fp32r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_hang_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_hang_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_hang_fp64r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void tiled_hang_fp32r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 
 hipError_t launch_load(double* f, const int64_t* idx, const double* val, int64_t nnz, const LoadParams& L,
                        double t, hipStream_t s);

@@ -118,20 +118,21 @@ hipError_t launch_finite32(const float* a, int64_t n, int32_t* flag, hipStream_t
 
 hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& hook) {
   const bool batch = L.refs != nullptr;
-  if (L.n_pure8 > 0) {
-    hook(1, true, s);
-    tiled_pure8_launch(L, batch ? L.work8 : nullptr, 0, L.n_pure8, s);
-    hook(1, false, s);
-  }
-  if (L.n_mixed > 0) {
+  // hanging-node cells first: their rows land in the partial-force slots of the owner tiles
+  if (L.n_hang > 0) {
     hook(2, true, s);
-    const TileWork* w = batch ? L.work_mixed : nullptr;
-    const int64_t first = batch ? 0 : L.n_pure8;
+    const TileWork* w = batch ? L.work_hang : nullptr;
     if (L.fp32)
-      (L.reduced ? tiled_mixed_fp32r_launch : tiled_mixed_fp32_launch)(L, w, first, L.n_mixed, s);
+      (L.reduced ? tiled_hang_fp32r_launch : tiled_hang_fp32_launch)(L, w, 0, L.n_hang, s);
     else
-      (L.reduced ? tiled_mixed_fp64r_launch : tiled_mixed_fp64_launch)(L, w, first, L.n_mixed, s);
+      (L.reduced ? tiled_hang_fp64r_launch : tiled_hang_fp64_launch)(L, w, 0, L.n_hang, s);
     hook(2, false, s);
+  }
+  // then every owner tile: regular cells, the partial forces, the update
+  if (L.n_tiles > 0) {
+    hook(1, true, s);
+    tiled_pure8_launch(L, batch ? L.work8 : nullptr, 0, L.n_tiles, s);
+    hook(1, false, s);
   }
   return hipGetLastError();
 }
@@ -149,7 +150,7 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 #undef SBFEM_L
 }
 
-// pure 8-node owner tiles
+// owner-tile pass
 void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
   const int64_t blocks = 8 * ((count + 7) / 8);
 #define SBFEM_L(F, R)                                                                                           \

@@ -1,16 +1,17 @@
-// Kernels for tiles with hanging-node cells, FP64 element products, reduced state / 16-bit forms (own unit: long compile).
+// Hanging-cell pass, FP64 element products, reduced state / 16-bit forms (own unit: long compile).
 #include "tiled_kernel.h"
 
 namespace sbfem {
 
-void tiled_mixed_fp64r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count,
-                             hipStream_t s) {
-  const int64_t blocks = 8 * ((count + 7) / 8);
-  if (L.lds > 65536)
-    (void)hipFuncSetAttribute((const void*)tiled_step<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)L.lds);
-  hipLaunchKernelGGL((tiled_step<false, true>), dim3((unsigned)blocks), dim3(L.threads_mixed), L.lds, s, L.single,
-                     L.refs, work, first, count, L.k, (int)L.force_only);
+void tiled_hang_fp64r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count,
+                              hipStream_t s) {
+  const int64_t per_block = L.threads_mixed / 64;  // one wave per item
+  const int64_t blocks = (count + per_block - 1) / per_block;
+  if (L.lds_hang > 65536)
+    (void)hipFuncSetAttribute((const void*)tiled_hang<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)L.lds_hang);
+  hipLaunchKernelGGL((tiled_hang<false, true>), dim3((unsigned)blocks), dim3(L.threads_mixed), L.lds_hang, s, L.single, L.refs,
+                     work, first, count, L.k);
 }
 
 }  // namespace sbfem

@@ -226,6 +226,16 @@ struct sbfem_mesh {
   int64_t n_pure8 = 0, n_mixed = 0;
   int32_t lds_bytes = 0;
   sbfem::TiledArgs* d_args = nullptr;   // two argument blocks: (u=buf0, prev=buf1) and swapped
+  sbfem::HangItem* hitems = nullptr;    // hanging-cell pass
+  int32_t* hconn = nullptr;
+  uint8_t* horient = nullptr;
+  uint8_t* hlevel = nullptr;
+  uint8_t* hmaterial = nullptr;
+  sbfem::HangPair* hpairs = nullptr;    // per owner tile: (owned dof, result index) of hanging rows
+  double* hres = nullptr;               // row forces of the hanging cells (hanging-cell pass output)
+  int64_t n_hang = 0;
+  int64_t lds_hang = 0;                 // LDS of a hanging-pass block (its pattern's matrix)
+  int32_t tile_nodes = 0;
   double* dWs64 = nullptr;              // Walsh blocks times s_e per scale class (pure 8-node tiles)
   float* dWs32 = nullptr;
   void* buf0 = nullptr;
@@ -508,6 +518,13 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->alloc, m->nodelist);
   dfree(m->alloc, m->tloads);
   dfree(m->alloc, m->d_args);
+  dfree(m->alloc, m->hitems);
+  dfree(m->alloc, m->hconn);
+  dfree(m->alloc, m->horient);
+  dfree(m->alloc, m->hlevel);
+  dfree(m->alloc, m->hmaterial);
+  dfree(m->alloc, m->hpairs);
+  dfree(m->alloc, m->hres);
   dfree(m->alloc, m->dWs64);
   dfree(m->alloc, m->dWs32);
   delete m;
@@ -554,11 +571,15 @@ static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const void* u, void*
   sbfem::TiledArgs a{};
   a.tiles = m->otiles;
   a.n_tiles = m->n_pure8 + m->n_mixed;
+  a.hitems = m->hitems;
+  a.hconn = m->hconn;
+  a.horient = m->horient;
+  a.hlevel = m->hlevel;
+  a.hmaterial = m->hmaterial;
+  a.hpairs = m->hpairs;
+  a.hres = m->hres;
   a.items = m->items;
   a.lidx = m->lidx;
-  a.orient = m->orient;
-  a.level = m->level;
-  a.material = m->material;
   a.nodelist = m->nodelist;
   a.loads = m->tloads;
   a.matE = m->matE;
@@ -591,8 +612,9 @@ static sbfem::TiledLaunch tiled_launch(const sbfem_mesh* m, bool force_only) {
   L.single.args = m->d_args;
   L.single.step = m->step;
   L.single.parity = tiled_parity(m);
-  L.n_pure8 = m->n_pure8;
-  L.n_mixed = m->n_mixed;
+  L.n_tiles = m->n_pure8 + m->n_mixed;
+  L.n_hang = m->n_hang;
+  L.lds_hang = (size_t)m->lds_hang;
   L.fp32 = m->prod != SBFEM_PROD_FP64;  // FP32 kernels also carry the 16-bit product forms
   L.reduced = m->state_mode != SBFEM_STATE_FP64 || m->prod == SBFEM_PROD_FP16 || m->prod == SBFEM_PROD_BF16;
   L.force_only = force_only;
@@ -810,30 +832,98 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     }
     m->n_pure8 = to.n_pure8;
     m->n_mixed = to.n_mixed;
+    m->tile_nodes = to.tile_nodes;
+    // hanging-node cells (every cell that is not a regular 8-node cell), each once: items of up
+    // to a wave of cells of one pattern, in cell order within a pattern; node ids slot-major
+    std::vector<int64_t> hcells;
+    for (int64_t c = 0; c < C; ++c)
+      if (ti.p8 < 0 || d->pattern[c] != ti.p8) hcells.push_back(c);
+    std::stable_sort(hcells.begin(), hcells.end(),
+                     [&](int64_t x, int64_t y) { return d->pattern[x] < d->pattern[y]; });
+    std::vector<sbfem::HangItem> hitems;
+    std::vector<int32_t> hconn;
+    std::vector<uint8_t> hor, hlev, hmat;
+    // the items of one hanging-pass block share a pattern: each pattern's items are padded with
+    // empty items to whole blocks; the block stages that pattern's matrix in LDS
+    const int per_block = m->block_threads_mixed / sbfem::kWave;
+    int64_t n_res = 0;  // result slots: 64 per row of every item
+    std::vector<std::pair<int64_t, sbfem::HangPair>> tpairs;  // (tile, pair)
+    int64_t kl_max = 0;  // entries of the largest staged matrix (rows padded to 4)
+    for (size_t i0 = 0; i0 < hcells.size();) {
+      const int pid = d->pattern[hcells[i0]];
+      size_t i1 = i0;
+      while (i1 < hcells.size() && i1 - i0 < (size_t)sbfem::kWave && d->pattern[hcells[i1]] == pid) ++i1;
+      sbfem::HangItem it{};
+      it.res0 = n_res;
+      it.cell0 = (int64_t)hor.size();
+      it.conn0 = (int64_t)hconn.size();
+      it.koff = p->koff[pid];
+      it.nn = p->ndof[pid] / 3;
+      it.count = (int32_t)(i1 - i0);
+      for (int k = 0; k < it.nn; ++k)
+        for (size_t j = i0; j < i1; ++j) hconn.push_back(iconn[cptr[hcells[j]] + k]);
+      for (size_t j = i0; j < i1; ++j) {
+        hor.push_back(orient[hcells[j]]);
+        hlev.push_back(d->level[hcells[j]]);
+        hmat.push_back(d->material[hcells[j]]);
+      }
+      hitems.push_back(it);
+      const int64_t nd = p->ndof[pid];
+      // row r of lane j: dof 3 g_k + pi(a) (r = 3k + a) of the tile that owns node g_k
+      for (size_t j = i0; j < i1; ++j) {
+        const int64_t c = hcells[j];
+        int pi[3];
+        double sg[3];
+        decode(orient[c], pi, sg);
+        for (int r = 0; r < nd; ++r) {
+          const int64_t g = iconn[cptr[c] + r / 3];
+          const int64_t t = g / to.tile_nodes;
+          const int64_t ri = n_res + (int64_t)r * sbfem::kWave + (int64_t)(j - i0);
+          tpairs.push_back({t, {(int32_t)(3 * (g - t * to.tile_nodes) + pi[r % 3]), (uint32_t)ri}});
+        }
+      }
+      n_res += nd * sbfem::kWave;
+      kl_max = std::max<int64_t>(kl_max, nd * ((nd + 3) & ~3));
+      i0 = i1;
+      if (i0 == hcells.size() || d->pattern[hcells[i0]] != pid) {
+        sbfem::HangItem pad = it;
+        pad.count = 0;
+        while (hitems.size() % per_block) hitems.push_back(pad);
+      }
+    }
+    m->n_hang = (int64_t)hitems.size();
+    m->lds_hang = kl_max * (d->prod == SBFEM_PROD_FP64 ? 8 : 4);
+    if (n_res > (int64_t)UINT32_MAX) {
+      sbfem_destroy_mesh(m);
+      return fail(SBFEM_EINVAL, "too many hanging-node cells for 32-bit result indices");
+    }
+    // pairs grouped by owner tile (each tile's pairs in result order)
+    std::stable_sort(tpairs.begin(), tpairs.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    std::vector<sbfem::HangPair> hpairs(tpairs.size());
+    for (size_t i = 0; i < tpairs.size(); ++i) {
+      hpairs[i] = tpairs[i].second;
+      auto& ot = to.tiles[tpairs[i].first];
+      if (ot.n_hpair == 0) ot.hpair0 = (int64_t)i;
+      ot.n_hpair++;
+    }
+    std::vector<std::pair<int64_t, sbfem::HangPair>>().swap(tpairs);
     m->layout[0] = to.n_pure8;
     m->layout[1] = to.n_mixed;
     m->layout[2] = (int64_t)to.items.size();
     m->layout[3] = (int64_t)to.nodelist.size() + N;
-    m->layout[4] = (int64_t)to.orient.size();  // cell entries of generic tiles
-    for (int64_t t = 0; t < to.n_pure8; ++t)       // plus those of pure 8-node tiles
-      for (int32_t w = 0; w < to.tiles[t].n_items; ++w) m->layout[4] += to.items[to.tiles[t].item0 + w].count;
+    m->layout[4] = (int64_t)hcells.size();  // regular cell entries over all tiles, plus the hanging cells
+    for (const auto& it : to.items) m->layout[4] += it.count;
     m->layout[5] = to.tile_nodes;
-    // algorithmic bytes per step of each kernel (the method's own traffic, whatever the layout):
-    // per owned dof u_n, u_{n-1}, M^-1 read and u_{n+1} written (8 B each); per cell its node
-    // ids (4 B each) and orientation, level, material (1 B each), counted in the tile that owns
-    // the cell's lowest node; per load entry 16 B
+    // algorithmic bytes per step of each pass (the method's own traffic, whatever the layout):
+    // the owner-tile pass reads u_n, u_{n-1}, M^-1 and writes u_{n+1} of every dof (8 B each),
+    // the node ids (4 B each) and orientation, level, material (1 B each) of the regular
+    // 8-node cells, and the load entries (16 B); the hanging-cell pass the same per-cell
+    // bytes of the other cells
     {
-      const int64_t tn = to.tile_nodes;
-      std::vector<char> pure((N + tn - 1) / tn, 0);
-      for (int64_t t = 0; t < to.n_pure8; ++t) pure[to.tiles[t].own0 / tn] = 1;
-      int64_t b8 = 0, bo = 0;
-      for (const auto& t : to.tiles) (pure[t.own0 / tn] ? b8 : bo) += 3 * (int64_t)t.n_own * 32;
-      for (int64_t c = 0; c < C; ++c) {
-        int32_t lo = iconn[cptr[c]];
-        for (int64_t i = cptr[c] + 1; i < cptr[c + 1]; ++i) lo = std::min(lo, iconn[i]);
-        (pure[lo / tn] ? b8 : bo) += 4 * (cptr[c + 1] - cptr[c]) + 3;
-      }
-      for (auto dof : bidx) (pure[(dof / 3) / tn] ? b8 : bo) += 16;
+      int64_t b8 = 32 * ndof + 16 * (int64_t)bidx.size(), bo = 0;
+      for (int64_t c = 0; c < C; ++c)
+        (ti.p8 >= 0 && d->pattern[c] == ti.p8 ? b8 : bo) += 4 * (cptr[c + 1] - cptr[c]) + 3;
       m->layout[6] = b8;
       m->layout[7] = bo;
     }
@@ -844,10 +934,20 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     ALLOC(lidx, to.lidx.size())
     ALLOC(nodelist, to.nodelist.size())
     ALLOC(tloads, to.loads.size())
-    ALLOC(orient, to.orient.size())
-    ALLOC(level, to.level.size())
-    ALLOC(material, to.material.size())
+    ALLOC(hitems, hitems.size())
+    ALLOC(hconn, hconn.size())
+    ALLOC(horient, hor.size())
+    ALLOC(hlevel, hlev.size())
+    ALLOC(hmaterial, hmat.size())
+    ALLOC(hpairs, std::max<size_t>(1, hpairs.size()))
+    ALLOC(hres, std::max<int64_t>(1, n_res))
     ALLOC(d_args, 2)
+    H2D(m->hitems, hitems.data(), hitems.size() * sizeof(sbfem::HangItem));
+    H2D(m->hconn, hconn.data(), hconn.size() * 4);
+    H2D(m->horient, hor.data(), hor.size());
+    H2D(m->hlevel, hlev.data(), hlev.size());
+    H2D(m->hmaterial, hmat.data(), hmat.size());
+    H2D(m->hpairs, hpairs.data(), hpairs.size() * sizeof(sbfem::HangPair));
     // structured Walsh table pre-multiplied by s_e = E h of each scale class (one rounding per entry)
     const size_t ncls = to.scale_keys.size();
     const int WC = sbfem::kWalshC;
@@ -876,9 +976,6 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     H2D(m->lidx, to.lidx.data(), to.lidx.size() * 2);
     H2D(m->nodelist, to.nodelist.data(), to.nodelist.size() * 4);
     H2D(m->tloads, to.loads.data(), to.loads.size() * sizeof(sbfem::LoadEntry));
-    H2D(m->orient, to.orient.data(), to.orient.size());
-    H2D(m->level, to.level.data(), to.level.size());
-    H2D(m->material, to.material.data(), to.material.size());
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers of `to` die below
   } else {
     // colours: greedy in input order, per-node mask of the colours already touching it
@@ -1116,8 +1213,8 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
   }
   int64_t tot8 = 0, totm = 0, most = 0;
   for (size_t i = 0; i < n; ++i) {
-    tot8 += g[i]->n_pure8;
-    totm += g[i]->n_mixed;
+    tot8 += g[i]->n_pure8 + g[i]->n_mixed;
+    totm += g[i]->n_hang;
     most = std::max(most, steps[i]);
   }
   sbfem::MeshRef* d_refs = nullptr;
@@ -1133,10 +1230,14 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
   sbfem::TiledLaunch L = tiled_launch(g[0], false);
   L.refs = d_refs;
   L.work8 = d_w8;
-  L.work_mixed = d_wm;
-  size_t lds = 0;
-  for (auto* m : g) lds = std::max(lds, (size_t)m->lds_bytes);
+  L.work_hang = d_wm;
+  size_t lds = 0, lds_hang = 0;
+  for (auto* m : g) {
+    lds = std::max(lds, (size_t)m->lds_bytes);
+    lds_hang = std::max(lds_hang, (size_t)m->lds_hang);
+  }
   L.lds = lds;
+  L.lds_hang = lds_hang;
   for (int64_t k = 0; k < most && e == hipSuccess; ++k) {
     // active set changes only when a mesh runs out of steps
     bool change = built_for < 0;
@@ -1148,8 +1249,8 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
       wm.clear();
       for (size_t i = 0; i < n; ++i) {
         if (k >= steps[i]) continue;
-        for (int64_t t = 0; t < g[i]->n_pure8; ++t) w8.push_back({(int32_t)i, 0, t});
-        for (int64_t t = 0; t < g[i]->n_mixed; ++t) wm.push_back({(int32_t)i, 0, g[i]->n_pure8 + t});
+        for (int64_t t = 0; t < g[i]->n_pure8 + g[i]->n_mixed; ++t) w8.push_back({(int32_t)i, 0, t});
+        for (int64_t t = 0; t < g[i]->n_hang; ++t) wm.push_back({(int32_t)i, 0, t});
       }
       if (e == hipSuccess && !w8.empty())
         e = hipMemcpyAsync(d_w8, w8.data(), w8.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
@@ -1158,8 +1259,8 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
       built_for = k;
     }
     L.k = k;
-    L.n_pure8 = (int64_t)w8.size();
-    L.n_mixed = (int64_t)wm.size();
+    L.n_tiles = (int64_t)w8.size();
+    L.n_hang = (int64_t)wm.size();
     if (e == hipSuccess) e = sbfem::launch_tiled(L, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);

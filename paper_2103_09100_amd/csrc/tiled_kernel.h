@@ -4,16 +4,20 @@
 #include "device_common.h"
 
 // =============================================================================================
-// Owner-tile step: one block per tile, everything in one pass (Alg. 1 time loop).
+// A time step (Alg. 1 time loop) is two passes.
+//  Hanging-cell pass: every cell that is not a regular 8-node cell, once, in items of one
+//    pattern: gather u_e, orient (Sec. 3.2.2), dense master product (eqs. Rinte, Rintep,
+//    KM_scale); the force of every row is stored (no atomics) for the owner tiles.
+//  Owner-tile pass, one block per tile:
 //   1. stage u_n of the tile's local nodes in LDS, clear the owned forces;
 //   2. add -P(t_n) b on owned load dofs;
-//   3. each wave takes cell items: gather u_e from LDS, multiply by the master
-//      matrix (eqs. Rinte, Rintep, KM_scale), add the rows of owned nodes into
-//      the LDS force array with FP64 LDS atomics;
-//   4. central-difference update of the owned dofs (eq. DnMdiag), or, force-only,
-//      write R_int of the owned dofs.
-// Blocks are mapped so that each XCD (blocks b, b+8, ...) walks a contiguous run
-// of tiles, which keeps neighbouring tiles' shared nodes in one L2.
+//   3. each wave takes items of regular 8-node cells: gather u_e from LDS, Walsh-form
+//      product, add the rows of owned nodes with FP64 LDS atomics;
+//   4. add the hanging-cell forces of its owned dofs (a list of (dof, result) pairs), then
+//      the central-difference update of the owned dofs (eq. DnMdiag), or, force-only, write
+//      R_int of the owned dofs.
+// Blocks are mapped so that each XCD (blocks b, b+8, ...) walks a contiguous run of tiles,
+// which keeps neighbouring tiles' shared nodes in one L2.
 
 namespace sbfem {
 
@@ -146,18 +150,28 @@ __device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&f
     for (int k = 0; k < 8; ++k) fe[3 * k + a] = y[a][k];
 }
 
-// Staged displacement of a local node: FP32 products keep 4 floats per node (x, y, z, pad)
-// so one 16-byte read fetches it; FP64 products 3 doubles.
-template <bool FP32>
-struct LdsNode {
-  static constexpr int stride = FP32 ? 4 : 3;
-};
-
-// A regular 8-node cell of a kind-1 item: gather, structured Walsh product with the
-// class-scaled table, FP64 LDS atomics into the rows of owned corners.
-// the lane's 16-byte record of local node indices in a kind-1 item
+// the lane's 16-byte record of local node indices in a regular-cell item
 __device__ __forceinline__ uint4 cell8_record(const TiledArgs& a, const CellItem& it, int lane) {
   return load_global(as_global(reinterpret_cast<const uint4*>(a.lidx)) + ((it.lidx0 >> 3) + lane));
+}
+
+// A regular 8-node cell: gather from the staged u (FP32: 16-byte float4 nodes, FP64: 3
+// doubles), structured Walsh product with the class-scaled table, FP64 LDS atomics into the
+// rows of owned corners.
+template <bool FP32, bool RED>
+__device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, const uint4 q, int n_own,
+                                      const typename LdsType<FP32>::T* __restrict__ ul, double* __restrict__ fl);
+
+// Precision forms: kernels instantiated with RED = false take FP64 state and no 16-bit
+// rounding as compile-time constants (the plain and mixed paths); RED = true reads them from
+// the argument block.
+template <bool RED>
+__device__ __forceinline__ int32_t state_of(const TiledArgs& a) {
+  return RED ? a.state : 0;
+}
+template <bool RED>
+__device__ __forceinline__ int32_t round_of(const TiledArgs& a) {
+  return RED ? a.round16 : 0;
 }
 
 template <bool FP32, bool RED>
@@ -194,108 +208,29 @@ __device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, co
   }
 }
 
-// Precision forms: kernels instantiated with RED = false take FP64 state and no 16-bit
-// rounding as compile-time constants (the plain and mixed paths); RED = true reads them from
-// the argument block.
-template <bool RED>
-__device__ __forceinline__ int32_t state_of(const TiledArgs& a) {
-  return RED ? a.state : 0;
-}
-template <bool RED>
-__device__ __forceinline__ int32_t round_of(const TiledArgs& a) {
-  return RED ? a.round16 : 0;
-}
-
-// The block's tile: which mesh (single or batched launch), its argument block for
-// this step (u and u_prev swap roles every step) and the tile index.  false: no tile.
-__device__ __forceinline__ bool block_tile(const MeshRef& single, const MeshRef* refs, const TileWork* work,
-                                           int64_t first, int64_t count, int64_t k, TiledArgs& a,
-                                           int64_t& ti, int64_t& step) {
-  // XCD-contiguous block -> tile map
-  const int64_t per = (count + 7) / 8;
-  const int64_t b = blockIdx.x;
-  const int64_t t = (b % 8) * per + b / 8;
+// The mesh of a block (single or batched launch), its argument block for this step (u and
+// u_prev swap roles every step), the index of its work unit (tile or hanging-cell item),
+// and the step number.  unit_of_block: XCD-contiguous map of blocks onto units.
+__device__ __forceinline__ bool block_unit(const MeshRef& single, const MeshRef* refs, const TileWork* work,
+                                           int64_t first, int64_t count, int64_t k, int64_t t, TiledArgs& a,
+                                           int64_t& ui, int64_t& step) {
   if (t >= count) return false;
   MeshRef r = single;
-  ti = first + t;
+  ui = first + t;
   if (work) {
     const TileWork w = load_const(as_const(work) + (first + t));
     r = load_const(as_const(refs) + w.mesh);
-    ti = w.tile;
+    ui = w.tile;
   }
   // k steps after the step recorded in the mesh ref (batched calls advance every mesh together)
   step = r.step + k;
   a = load_const(as_const(r.args) + ((r.parity + k) & 1));
   return true;
 }
-
-// Generic cell of NN nodes (any pattern): orientation per cell, dense master matrix,
-// scale s_e per cell.
-template <int NN, bool FP32, bool RED>
-__device__ __forceinline__ void tile_cell(const TiledArgs& a, const CellItem& it, int lane, int n_own,
-                                          const typename LdsType<FP32>::T* __restrict__ ul,
-                                          double* __restrict__ fl) {
-  constexpr int ND = 3 * NN;
-  using T = typename LdsType<FP32>::T;
-  const int64_t cell = it.cell0 + lane;
-  int p0, p1, p2;
-  double s0, s1, s2;
-  decode_orient(as_global(a.orient)[cell], p0, p1, p2, s0, s1, s2);
-  const double se = as_const(a.matE)[as_global(a.material)[cell]] * ldexp(a.h0, -(int)as_global(a.level)[cell]);
-  int li[NN];
-  gptr_t<uint16_t> lidx = as_global(a.lidx);
-#pragma unroll
-  for (int k = 0; k < NN; ++k) li[k] = lidx[it.lidx0 + (int64_t)k * it.count + lane];
-  const uint32_t mask = it.mask;
-  // oriented nodal displacements; the FP32 path also removes the rigid translation of
-  // node 0 (K_p annihilates it) so that only differences across the cell are rounded
-  T ue[ND];
-  {
-    T rx = 0, ry = 0, rz = 0;
-    if constexpr (FP32) {
-      const T* q0 = ul + LdsNode<FP32>::stride * li[0];
-      rx = q0[0];
-      ry = q0[1];
-      rz = q0[2];
-    }
-#pragma unroll
-    for (int k = 0; k < NN; ++k) {
-      const T* q = ul + LdsNode<FP32>::stride * li[k];
-      const T x = q[0] - rx, y = q[1] - ry, z = q[2] - rz;
-      ue[3 * k + 0] = (T)s0 * pick3t<T>(p0, x, y, z);
-      ue[3 * k + 1] = (T)s1 * pick3t<T>(p1, x, y, z);
-      ue[3 * k + 2] = (T)s2 * pick3t<T>(p2, x, y, z);
-    }
-  }
-  double post = se;  // applied to each product row
-  if constexpr (FP32) {
-    const int32_t rm = round_of<RED>(a);
-    if (rm) {  // 16-bit operands: scale by a power of two, round, undo the scale after
-      float mx = 0.0f;
-#pragma unroll
-      for (int j = 0; j < ND; ++j) mx = fmaxf(mx, fabsf(ue[j]));
-      const float su = pow2_scale(mx);
-#pragma unroll
-      for (int j = 0; j < ND; ++j) ue[j] = round16(ue[j] * su, rm);
-      post = se / (double)su;
-    }
-  }
-  cptr_t<T> Kp = as_const(FP32 ? (const T*)(a.K32 + it.koff) : (const T*)(a.K64 + it.koff));
-#pragma unroll
-  for (int k = 0; k < NN; ++k) {
-    if (!((mask >> k) & 1u)) continue;  // uniform in the wave
-    const bool own = li[k] < n_own;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int i = 3 * k + c;
-      T acc = 0;
-#pragma unroll
-      for (int j = 0; j < ND; ++j) acc = fma(Kp[i * ND + j], ue[j], acc);
-      const int pc = c == 0 ? p0 : (c == 1 ? p1 : p2);
-      const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
-      if (own) atomicAdd(fl + 3 * li[k] + pc, sc * post * (double)acc);
-    }
-  }
+__device__ __forceinline__ int64_t xcd_unit(int64_t count) {
+  const int64_t per = (count + 7) / 8;
+  const int64_t b = blockIdx.x;
+  return (b % 8) * per + b / 8;
 }
 
 // Owned forces start at -P(t_n) b on the tile's load dofs.
@@ -307,8 +242,20 @@ __device__ __forceinline__ void tile_loads(const TiledArgs& a, const OwnerTile& 
   }
 }
 
-// Central-difference update of the owned dofs written over u_{n-1} (or R_int, force-only).
-// un_lds: u_n of the owned dofs as staged (FP64 staging holds u_n itself).
+// Forces of hanging-node cells on the tile's owned dofs, from the hanging-cell pass.
+__device__ __forceinline__ void tile_hang_forces(const TiledArgs& a, const OwnerTile& tile, double* fl, int tid,
+                                                 int nt) {
+  const gptr_t<HangPair> pr = as_global(a.hpairs) + tile.hpair0;
+  const gptr_t<double> res = as_global((const double*)a.hres);
+  for (int i = tid; i < tile.n_hpair; i += nt) {
+    const HangPair h = load_global(pr + i);
+    atomicAdd(fl + h.ldof, res[h.res]);
+  }
+}
+
+// Central-difference update of the owned dofs written over u_{n-1} (or R_int, force-only),
+// after adding and clearing the tile's partial forces.  un_lds: u_n of the owned dofs as
+// staged (FP64 staging holds u_n itself).
 template <bool FP32, bool RED>
 __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile& tile, const double* fl,
                                             const double* un_lds, int force_only, int tid, int nt) {
@@ -323,9 +270,10 @@ __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile&
   for (int i = tid; i < n; i += nt) {
     const int64_t d = d0 + i;
     const int32_t sm = state_of<RED>(a);
+    const double r = fl[i];
     const double un = FP32 ? state_load(a.u, sm, a.ndof, d) : un_lds[i];
     const double up = state_load(a.um1, sm, a.ndof, d);
-    const double v = (a.dt2 * minv_load(a.minv, sm, d) * (-fl[i]) + 2.0 * un - (1.0 - a.c) * up) * inv;
+    const double v = (a.dt2 * minv_load(a.minv, sm, d) * (-r) + 2.0 * un - (1.0 - a.c) * up) * inv;
     state_store(a.um1, sm, a.ndof, d, v);
   }
 }
@@ -361,69 +309,127 @@ __device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& 
   for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0;
 }
 
-// Tiles with cells of any pattern: kind-1 items take the 8-node path, the others the
-// dense product of their pattern.  LDS: the owned forces (FP64), then the staged u.
+// Hanging-node cell of NN nodes in the hanging-cell pass: u_e gathered from global memory,
+// oriented, 16-bit operands if asked, dense master product over all rows scaled by s_e;
+// row i of the item's lane goes to hres[res0 + 64 i + lane] (the owner tiles add it).
+template <int NN>
+constexpr int k_row_stride() {
+  return (3 * NN + 3) & ~3;
+}
+
+template <int NN, bool FP32, bool RED>
+__device__ __forceinline__ void hang_cell(const TiledArgs& a, const HangItem& it, int lane,
+                                          const typename LdsType<FP32>::T* __restrict__ Kl) {
+  constexpr int ND = 3 * NN;
+  constexpr int NDP = k_row_stride<NN>();
+  using T = typename LdsType<FP32>::T;
+  const int64_t cell = it.cell0 + lane;
+  int p0, p1, p2;
+  double s0, s1, s2;
+  decode_orient(as_global(a.horient)[cell], p0, p1, p2, s0, s1, s2);
+  const double se = as_const(a.matE)[as_global(a.hmaterial)[cell]] * ldexp(a.h0, -(int)as_global(a.hlevel)[cell]);
+  const gptr_t<int32_t> conn = as_global(a.hconn);
+  const int32_t sm = state_of<RED>(a);
+  int64_t g[NN];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) g[k] = conn[it.conn0 + (int64_t)k * it.count + lane];
+  // oriented nodal displacements; reduced products take differences to node 0 (K_p
+  // annihilates translations) so that only variations across the cell are rounded
+  T ue[ND];
+  {
+    double r[3] = {0.0, 0.0, 0.0};
+    if constexpr (FP32) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] = state_load(a.u, sm, a.ndof, 3 * g[0] + c);
+    }
+#pragma unroll
+    for (int k = 0; k < NN; ++k) {
+      const T x = (T)(state_load(a.u, sm, a.ndof, 3 * g[k] + 0) - r[0]);
+      const T y = (T)(state_load(a.u, sm, a.ndof, 3 * g[k] + 1) - r[1]);
+      const T z = (T)(state_load(a.u, sm, a.ndof, 3 * g[k] + 2) - r[2]);
+      ue[3 * k + 0] = (T)s0 * pick3t<T>(p0, x, y, z);
+      ue[3 * k + 1] = (T)s1 * pick3t<T>(p1, x, y, z);
+      ue[3 * k + 2] = (T)s2 * pick3t<T>(p2, x, y, z);
+    }
+  }
+  double post = se;  // applied to each product row
+  if constexpr (FP32) {
+    const int32_t rm = round_of<RED>(a);
+    if (rm) {  // 16-bit operands: scale by a power of two, round, undo the scale after
+      float mx = 0.0f;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) mx = fmaxf(mx, fabsf(ue[j]));
+      const float su = pow2_scale(mx);
+#pragma unroll
+      for (int j = 0; j < ND; ++j) ue[j] = round16(ue[j] * su, rm);
+      post = se / (double)su;
+    }
+  }
+  const gmut_t<double> res = as_global_mut(a.hres) + it.res0 + lane;
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int i = 3 * k + c;
+      T acc = 0;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) acc = fma(Kl[i * NDP + j], ue[j], acc);
+      const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
+      res[(int64_t)i * 64] = sc * post * (double)acc;  // to node k, component pi(c)
+    }
+  }
+}
+
+// Hanging-cell pass: one wave per item; the items of a block share one pattern (the set-up
+// pads every pattern's items to whole blocks), whose master matrix the block stages in LDS
+// once (rows padded to a multiple of 4 entries) so the waves read its rows as LDS broadcasts.
+// FP32 products are held to 128 VGPRs (4 waves per SIMD); the FP64 variant keeps the register
+// file (its spills would cost more).
 template <bool FP32, bool RED>
-__device__ __forceinline__ void tiled_step_body(MeshRef single, const MeshRef* __restrict__ refs,
-                                                const TileWork* __restrict__ work, int64_t first, int64_t count,
-                                                int64_t k, int force_only) {
+__global__ void __launch_bounds__(512, FP32 ? 4 : 1) tiled_hang(MeshRef single, const MeshRef* __restrict__ refs,
+                                                                 const TileWork* __restrict__ work, int64_t first,
+                                                                 int64_t count, int64_t k) {
   using T = typename LdsType<FP32>::T;
   extern __shared__ double lds[];
+  T* Kl = (T*)lds;
+  const int per_block = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int64_t t0 = (int64_t)blockIdx.x * per_block;
   TiledArgs a;
-  int64_t ti, step;
-  if (!block_tile(single, refs, work, first, count, k, a, ti, step)) return;
-  const OwnerTile tile = load_const(as_const(a.tiles) + ti);
-  const int n_own = tile.n_own;
-  double* fl = lds;
-  T* ul = (T*)(lds + 3 * (int64_t)n_own);
-  const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
-  __syncthreads();
-  if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
-  // the wave index is uniform in a wave: say so, so item fields (and K_p) come through scalar loads
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int n_waves = nt >> 6;
-  cptr_t<CellItem> items = as_const(a.items) + tile.item0;
-  for (int w = wave; w < tile.n_items; w += n_waves) {
-    const CellItem it = load_const(items + w);
-    if (lane >= it.count) continue;
-    if (it.kind == 1) {
-      cell8<FP32, RED>(a, it, cell8_record(a, it, lane), n_own, ul, fl);
-      continue;
+  int64_t ii, step;
+  if (!block_unit(single, refs, work, first, count, k, t0, a, ii, step)) return;  // uniform in the block
+  {
+    // the block's pattern: that of its first item (every item of the block has it)
+    const HangItem i0 = load_const(as_const(a.hitems) + ii);
+    const int nd = 3 * i0.nn, ndp = (nd + 3) & ~3;
+    const gptr_t<T> K = as_global(FP32 ? (const T*)(a.K32 + i0.koff) : (const T*)(a.K64 + i0.koff));
+    for (int e = threadIdx.x; e < nd * ndp; e += blockDim.x) {
+      const int r = e / ndp, c = e - r * ndp;
+      Kl[e] = c < nd ? K[r * nd + c] : T(0);
     }
-#define SBFEM_TCASE(N) \
-  case N:              \
-    tile_cell<N, FP32, RED>(a, it, lane, n_own, ul, fl); \
-    break;
-    switch (it.nn) {
-      SBFEM_TCASE(8) SBFEM_TCASE(9) SBFEM_TCASE(10) SBFEM_TCASE(11) SBFEM_TCASE(12) SBFEM_TCASE(13)
-      SBFEM_TCASE(14) SBFEM_TCASE(15) SBFEM_TCASE(16) SBFEM_TCASE(17) SBFEM_TCASE(18) SBFEM_TCASE(19)
-      SBFEM_TCASE(20) SBFEM_TCASE(21) SBFEM_TCASE(22) SBFEM_TCASE(23) SBFEM_TCASE(24) SBFEM_TCASE(25)
-      SBFEM_TCASE(26)
-      default:
-        break;
-    }
-#undef SBFEM_TCASE
   }
   __syncthreads();
-  // FP64 staging keeps u_n of the owned nodes at the start of ul (owned nodes come first)
-  tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
+  if (!block_unit(single, refs, work, first, count, k, t0 + wave, a, ii, step)) return;
+  const HangItem it = load_const(as_const(a.hitems) + ii);
+  if (lane >= it.count) return;
+#define SBFEM_TCASE(N) \
+  case N:              \
+    hang_cell<N, FP32, RED>(a, it, lane, Kl); \
+    break;
+  switch (it.nn) {
+    SBFEM_TCASE(8) SBFEM_TCASE(9) SBFEM_TCASE(10) SBFEM_TCASE(11) SBFEM_TCASE(12) SBFEM_TCASE(13)
+    SBFEM_TCASE(14) SBFEM_TCASE(15) SBFEM_TCASE(16) SBFEM_TCASE(17) SBFEM_TCASE(18) SBFEM_TCASE(19)
+    SBFEM_TCASE(20) SBFEM_TCASE(21) SBFEM_TCASE(22) SBFEM_TCASE(23) SBFEM_TCASE(24) SBFEM_TCASE(25)
+    SBFEM_TCASE(26)
+    default:
+      break;
+  }
+#undef SBFEM_TCASE
 }
 
-// The kernel of the tiles with hanging-node cells.  FP32 products are held to 128 VGPRs
-// (4 waves per SIMD): the rare large dense cells spill a little, the regular cells of these
-// tiles gain occupancy.  FP64 products keep the register file (their spills cost more).
-template <bool FP32, bool RED>
-__global__ void __launch_bounds__(512, FP32 ? 4 : 1) tiled_step(MeshRef single, const MeshRef* __restrict__ refs,
-                                                                 const TileWork* __restrict__ work, int64_t first,
-                                                                 int64_t count, int64_t k, int force_only) {
-  tiled_step_body<FP32, RED>(single, refs, work, first, count, k, force_only);
-}
-
-// Tiles whose cells are all regular 8-node cells in identity orientation (the master
-// matrix is invariant under the 48 cube transformations, so the set-up maps every such
-// cell onto it without a transformation): only kind-1 items.
+// Owner-tile pass over every tile.  Loads whose addresses are known at the start are issued
+// before the staging so that their latency overlaps it: the wave's first cell record and,
+// with FP64 state, the update operands of the thread's owned dofs (at most 3 per thread).
 template <bool FP32, bool RED>
 __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
                                                    const TileWork* __restrict__ work, int64_t first,
@@ -432,7 +438,7 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   extern __shared__ double lds[];
   TiledArgs a;
   int64_t ti, step;
-  if (!block_tile(single, refs, work, first, count, k, a, ti, step)) return;
+  if (!block_unit(single, refs, work, first, count, k, xcd_unit(count), a, ti, step)) return;
   const OwnerTile tile = load_const(as_const(a.tiles) + ti);
   const int n_own = tile.n_own;
   double* fl = lds;
@@ -442,9 +448,6 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int n_waves = nt >> 6;
   cptr_t<CellItem> items = as_const(a.items) + tile.item0;
-  // Loads whose addresses are known now are issued before the staging so that their latency
-  // overlaps it: the wave's first cell record and, with FP64 state, the update operands of
-  // the thread's owned dofs (at most 3 per thread).
   constexpr int kPre = 3;
   const int n_dof = 3 * n_own;
   const bool pre = !RED && !force_only && n_dof <= kPre * nt;
@@ -474,6 +477,7 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
+  tile_hang_forces(a, tile, fl, tid, nt);
   while (w < tile.n_items) {
     // the next record is requested before this cell's work
     const int wn = w + n_waves;
@@ -497,8 +501,9 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
     for (int j = 0; j < kPre; ++j) {
       const int i = tid + j * nt;
       if (i < n_dof) {
+        const double r = fl[i];
         const double un = FP32 ? pu[j] : (double)ul[i];
-        up[d0 + i] = (a.dt2 * pm[j] * (-fl[i]) + 2.0 * un - (1.0 - a.c) * pp[j]) * inv;
+        up[d0 + i] = (a.dt2 * pm[j] * (-r) + 2.0 * un - (1.0 - a.c) * pp[j]) * inv;
       }
     }
   } else {

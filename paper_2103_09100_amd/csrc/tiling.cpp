@@ -7,7 +7,7 @@
 // into wave-sized items of one pattern and one row mask so that the master
 // matrix and the row selection are uniform within a wave.
 //
-// Regular 8-node cells (pattern p8, identity orientation) form kind-1 items:
+// Regular 8-node cells (pattern p8, identity orientation) form the items:
 // one scale class (level, material) per item so the pre-scaled Walsh table is
 // uniform in a wave, full waves of cells in cell (Morton) order (the item's
 // mask is the union of the cells' owned-corner masks), and the eight local node
@@ -40,9 +40,8 @@ struct TileOut {
   std::vector<int32_t> local;      // global ids of local nodes (owned first)
   std::vector<CellItem> items;     // offsets relative to this tile
   std::vector<uint16_t> lidx;
-  std::vector<uint8_t> orient, level, material;
   std::vector<LoadEntry> loads;
-  bool pure8 = true;
+  bool pure8 = true;  // no hanging-node cell
 };
 
 }  // namespace
@@ -99,6 +98,11 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
     for (size_t j = 0; j < cells.size(); ++j) {
       const int32_t c = cells[j];
       uint32_t mask = 0;
+      if (in.p8 < 0 || in.pattern[c] != in.p8) {  // hanging-node cell: not staged in this tile
+        r.pure8 = false;
+        li_off[j + 1] = (int64_t)li_flat.size();
+        continue;
+      }
       for (int64_t i = in.cptr[c]; i < in.cptr[c + 1]; ++i) {
         const int32_t g = in.conn[i];
         int32_t l;
@@ -118,100 +122,31 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
         li_flat.push_back((uint16_t)l);
       }
       li_off[j + 1] = (int64_t)li_flat.size();
-      if (in.p8 < 0 || in.pattern[c] != in.p8) r.pure8 = false;
       recs.push_back({(int32_t)j, mask, (int32_t)in.pattern[c]});
     }
-    // regular 8-node cells (every cell of a pure tile): kind-1 items of one scale class, full
-    // waves with the union of the cells' owned-corner masks
-    std::vector<CellRec> r8, rg;
-    for (const auto& rc : recs) {
-      if (in.p8 >= 0 && in.pattern[cells[rc.c]] == in.p8)
-        r8.push_back({rc.c, rc.mask, cls[cells[rc.c]]});
-      else
-        rg.push_back(rc);
-    }
-    auto by_key = [](const CellRec& a, const CellRec& b) {
-      return a.pattern != b.pattern ? a.pattern < b.pattern : a.mask < b.mask;
-    };
-    // regular cells: by scale class, then in cell (Morton) order, so that the lanes of a wave hold
-    // neighbouring cells and their corner nodes spread over the LDS banks
+    // regular 8-node cells: items of one scale class in cell (Morton) order, so that the lanes
+    // of a wave hold neighbouring cells and their corner nodes spread over the LDS banks; full
+    // waves with the union of the cells' owned-corner masks.  The other cells of the tile
+    // (hanging-node cells) are handled by the hanging-cell pass.
+    std::vector<CellRec> r8;
+    for (const auto& rc : recs) r8.push_back({rc.c, rc.mask, cls[cells[rc.c]]});
     std::stable_sort(r8.begin(), r8.end(), [](const CellRec& a, const CellRec& b) { return a.pattern < b.pattern; });
-    std::stable_sort(rg.begin(), rg.end(), by_key);
-    // generic items: group by (pattern, row mask); small groups of one pattern share an item
-    const size_t kMerge = 16;
-    std::vector<std::vector<CellRec>> groups;
-    {
-      size_t i0 = 0;
-      std::vector<CellRec> small;
-      int32_t small_pat = -1;
-      auto flush_small = [&] {
-        if (!small.empty()) groups.push_back(small);
-        small.clear();
-      };
-      while (i0 < rg.size()) {
-        size_t i1 = i0;
-        while (i1 < rg.size() && rg[i1].pattern == rg[i0].pattern && rg[i1].mask == rg[i0].mask) ++i1;
-        std::vector<CellRec> g(rg.begin() + i0, rg.begin() + i1);
-        if (g.size() < kMerge) {
-          if (small_pat != g[0].pattern) flush_small();
-          small_pat = g[0].pattern;
-          small.insert(small.end(), g.begin(), g.end());
-        } else {
-          groups.push_back(g);
-        }
-        i0 = i1;
+    size_t i0 = 0;
+    while (i0 < r8.size()) {
+      size_t i1 = i0;
+      while (i1 < r8.size() && i1 - i0 < (size_t)kWave && r8[i1].pattern == r8[i0].pattern) ++i1;
+      CellItem it{};
+      it.lidx0 = (int64_t)r.lidx.size();
+      it.koff = (int64_t)kWalshC * r8[i0].pattern;
+      it.count = (int32_t)(i1 - i0);
+      it.mask = 0;
+      for (size_t b = i0; b < i1; ++b) {
+        it.mask |= r8[b].mask;
+        for (int k = 0; k < 8; ++k) r.lidx.push_back(li_flat[li_off[r8[b].c] + k]);
       }
-      flush_small();
+      r.items.push_back(it);
+      i0 = i1;
     }
-    for (auto& g : groups) {
-      for (size_t a = 0; a < g.size(); a += kWave) {
-        const size_t cnt = std::min<size_t>(kWave, g.size() - a);
-        CellItem it{};
-        const int32_t pid = g[a].pattern;
-        const int nn = in.pattern_ndof[pid] / 3;
-        it.lidx0 = (int64_t)r.lidx.size();
-        it.cell0 = (int64_t)r.orient.size();
-        it.koff = in.pattern_koff[pid];
-        it.nn = nn;
-        it.count = (int32_t)cnt;
-        it.mask = 0;
-        it.kind = 0;
-        for (size_t b = 0; b < cnt; ++b) it.mask |= g[a + b].mask;
-        for (int k = 0; k < nn; ++k)
-          for (size_t b = 0; b < cnt; ++b) r.lidx.push_back(li_flat[li_off[g[a + b].c] + k]);
-        for (size_t b = 0; b < cnt; ++b) {
-          const int32_t c = cells[g[a + b].c];
-          r.orient.push_back(in.orient[c]);
-          r.level.push_back(in.level[c]);
-          r.material.push_back(in.material[c]);
-        }
-        r.items.push_back(it);
-      }
-    }
-    // lane-major records start at a multiple of 8 entries (16 bytes)
-    while (r.lidx.size() % 8) r.lidx.push_back(0);
-    {
-      size_t i0 = 0;
-      while (i0 < r8.size()) {
-        size_t i1 = i0;
-        while (i1 < r8.size() && i1 - i0 < (size_t)kWave && r8[i1].pattern == r8[i0].pattern) ++i1;
-        CellItem it{};
-        it.lidx0 = (int64_t)r.lidx.size();
-        it.cell0 = 0;
-        it.koff = (int64_t)kWalshC * r8[i0].pattern;
-        it.nn = 8;
-        it.count = (int32_t)(i1 - i0);
-        it.mask = 0;
-        it.kind = 1;
-        for (size_t b = i0; b < i1; ++b) {
-          it.mask |= r8[b].mask;
-          for (int k = 0; k < 8; ++k) r.lidx.push_back(li_flat[li_off[r8[b].c] + k]);
-        }
-        r.items.push_back(it);
-        i0 = i1;
-      }
-    }
-    while (r.lidx.size() % 8) r.lidx.push_back(0);  // every tile's records start 16-byte aligned
     for (int64_t n = own0; n < own1; ++n)
       for (int a = 0; a < 3; ++a) {
         auto it = bmap.find(3 * n + a);
@@ -219,43 +154,36 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
       }
   });
 
-  // concatenate: pure 8-node tiles first, then the others
+  // concatenate in tile order
   out.tile_nodes = tile_nodes;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int64_t t = 0; t < n_tiles; ++t) {
-      TileOut& r = res[t];
-      if (r.pure8 != (pass == 0)) continue;
-      OwnerTile ot{};
-      ot.own0 = t * tile_nodes;
-      ot.n_own = (int32_t)std::min<int64_t>(tile_nodes, N - ot.own0);
-      ot.node0 = (int64_t)out.nodelist.size();
-      ot.n_local = (int32_t)r.local.size();
-      ot.item0 = (int64_t)out.items.size();
-      ot.n_items = (int32_t)r.items.size();
-      ot.load0 = (int32_t)out.loads.size();
-      ot.n_load = (int32_t)r.loads.size();
-      out.max_local = std::max<int64_t>(out.max_local, ot.n_local);
-      if (ot.n_local > 65535) return false;
-      const int64_t lbase = (int64_t)out.lidx.size(), cbase = (int64_t)out.orient.size();
-      for (auto it : r.items) {
-        it.lidx0 += lbase;
-        it.cell0 += cbase;
-        out.items.push_back(it);
-      }
-      // owned nodes are implicit (own0 + i); only the others are listed
-      out.nodelist.insert(out.nodelist.end(), r.local.begin() + ot.n_own, r.local.end());
-      out.lidx.insert(out.lidx.end(), r.lidx.begin(), r.lidx.end());
-      out.orient.insert(out.orient.end(), r.orient.begin(), r.orient.end());
-      out.level.insert(out.level.end(), r.level.begin(), r.level.end());
-      out.material.insert(out.material.end(), r.material.begin(), r.material.end());
-      out.loads.insert(out.loads.end(), r.loads.begin(), r.loads.end());
-      out.tiles.push_back(ot);
-      if (pass == 0)
-        out.n_pure8++;
-      else
-        out.n_mixed++;
-      r = TileOut();
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    TileOut& r = res[t];
+    OwnerTile ot{};
+    ot.own0 = t * tile_nodes;
+    ot.n_own = (int32_t)std::min<int64_t>(tile_nodes, N - ot.own0);
+    ot.node0 = (int64_t)out.nodelist.size();
+    ot.n_local = (int32_t)r.local.size();
+    ot.item0 = (int64_t)out.items.size();
+    ot.n_items = (int32_t)r.items.size();
+    ot.load0 = (int32_t)out.loads.size();
+    ot.n_load = (int32_t)r.loads.size();
+    out.max_local = std::max<int64_t>(out.max_local, ot.n_local);
+    if (ot.n_local > 65535) return false;
+    const int64_t lbase = (int64_t)out.lidx.size();
+    for (auto it : r.items) {
+      it.lidx0 += lbase;
+      out.items.push_back(it);
     }
+    // owned nodes are implicit (own0 + i); only the others are listed
+    out.nodelist.insert(out.nodelist.end(), r.local.begin() + ot.n_own, r.local.end());
+    out.lidx.insert(out.lidx.end(), r.lidx.begin(), r.lidx.end());
+    out.loads.insert(out.loads.end(), r.loads.begin(), r.loads.end());
+    out.tiles.push_back(ot);
+    if (r.pure8)
+      out.n_pure8++;
+    else
+      out.n_mixed++;
+    r = TileOut();
   }
   return true;
 }

@@ -19,7 +19,7 @@ struct TilingInput {
   const uint8_t* material = nullptr;
   const int32_t* pattern_ndof = nullptr;
   const int64_t* pattern_koff = nullptr;
-  // 8-node cells of this pattern (identity orientation) form the pure 8-node tiles; -1: none
+  // regular 8-node cells: this pattern (identity orientation); the others are hanging-node cells
   int32_t p8 = -1;
   std::vector<int64_t> load_dof;       // internal dofs
   std::vector<double> load_val;
@@ -27,13 +27,12 @@ struct TilingInput {
 
 struct TilingOutput {
   int32_t tile_nodes = 0;
-  std::vector<OwnerTile> tiles;        // n_pure8 tiles of 8-node cells only, then n_mixed
+  std::vector<OwnerTile> tiles;        // in node order; n_mixed of them own a hanging-cell node
   int64_t n_pure8 = 0, n_mixed = 0;
   int64_t max_local = 0;
   std::vector<CellItem> items;
   std::vector<int32_t> nodelist;
   std::vector<uint16_t> lidx;
-  std::vector<uint8_t> orient, level, material;
   std::vector<LoadEntry> loads;
   // scale classes of the pure 8-node tiles: key = level * 256 + material, in order of first use;
   // an item of such a tile carries koff = 72 * class
