@@ -348,6 +348,35 @@ def precision_sweep(torch, args):
                 steps=n_total, snapshot_every=every, load_ends_at_step=t_end, energy_steps=h_at, rows=rows)
 
 
+def small_mesh_latency(torch, steps=1000, graph_steps=50, prods=("fp64", "fp32")):
+    """Per-step time of the 2187-dof cube (launch-bound): steps launched one by one vs
+    replayed from a graph of `graph_steps` steps; the two final states are compared."""
+    from meshgen import configs
+    from paper_2103_09100_amd.solver import Simulation
+    stream = torch.cuda.Stream()
+    m = configs.cfg1()
+    out = {"workload": "cfg1: unit cube 8x8x8 cells, 2187 dofs, tiled assembly", "steps": steps,
+           "graph_steps": graph_steps}
+    for prod in prods:
+        row = {}
+        for label, g in (("direct", 0), ("graph", graph_steps)):
+            sim = Simulation(m, prod=prod, assembly="tiled", stream=stream.cuda_stream, graph_steps=g)
+            sim.step(2 * graph_steps)  # warm-up (captures the graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            row[label + "_us_per_step"] = (time.perf_counter() - t0) / steps * 1e6
+            row[label + "_u"] = sim.u()
+            sim.close()
+        row["rel_diff"] = float(np.abs(row.pop("graph_u") - row["direct_u"]).max() / np.abs(row["direct_u"]).max())
+        row.pop("direct_u")
+        out[prod] = row
+        log(f"[bench] cfg1 {prod}: {row['direct_us_per_step']:.1f} us/step launched, "
+            f"{row['graph_us_per_step']:.1f} us/step from graphs, diff {row['rel_diff']:.1e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +389,8 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--small", type=int, default=1000, help="steps of the small-mesh latency check (0: skip)")
+    ap.add_argument("--graph-steps", type=int, default=50, help="steps per captured graph")
     ap.add_argument("--serve-only", action="store_true", help="only the serving stream")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-quantum", type=int, default=50, help="steps per batched call")
@@ -486,6 +517,8 @@ def main():
         out["speedup_vs_fp64"] = r["value"] / results[fp64]["value"]
         ref = finals[fp64]
         out["rel_err_vs_fp64"] = float(np.abs(finals[head] - ref).max() / np.abs(ref).max())
+    if args.small > 0:
+        out["small_mesh_step_us"] = small_mesh_latency(torch, args.small, args.graph_steps)
     if args.serve > 0:
         out["serving"] = serving(torch, args)
         out["p99_latency_s"] = out["serving"]["budget"]["p99_s"]

@@ -155,6 +155,21 @@ sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream);
 sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream);
 
 /*
+ * Step loops in HIP graphs (owner-tile assembly only; the time loop of Alg. 1
+ * replayed from a captured graph instead of launched step by step).  With
+ * steps > 0, step_n runs every whole chunk of `steps` steps as one replay of a
+ * graph captured on first use (its launches read the step number from device
+ * memory, so one graph serves every chunk); sbfem_step_batch does the same for
+ * a group whose meshes all have steps > 0 (the smallest value is used), with
+ * the graph and work lists of each set of active meshes cached between calls
+ * (at most 16 sets; a mesh's entries go when it is destroyed or its value
+ * changes).  0 (the default) launches every step.  Not used while profiling is
+ * on.  Results equal those of direct launches (same kernels, same order).
+ * steps outside [0, 4096], or > 0 on another assembly: SBFEM_EINVAL.
+ */
+sbfem_status sbfem_set_graph_steps(sbfem_mesh* m, int32_t steps);
+
+/*
  * Copy state to host memory host_out [3N] (FP64):
  *   which = 0: u_n, 1: u_{n-1}, 2: R_int(u_n) = sum_e s_e R_e^T K_p R_e u_e (in the mesh's
  *   product precision), 3: the lumped diagonal mass M (Sec. 3.3; FP64, fixed dofs included).

@@ -35,7 +35,7 @@ ASM = {"atomic": 0, "colour": 1, "tiled": 2}
 LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
 
 EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint",
-           "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n",
+           "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n", "sbfem_set_graph_steps",
            "sbfem_step_batch", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
            "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_set_allocator",
            "sbfem_last_error"]
@@ -70,6 +70,7 @@ _lib.sbfem_destroy_mesh.argtypes = [_P]
 _lib.sbfem_destroy_mesh.restype = None
 _lib.sbfem_step_n.argtypes = [_P, C.c_int64, _P]
 _lib.sbfem_step_batch.argtypes = [_P, C.c_int32, _P, _P]
+_lib.sbfem_set_graph_steps.argtypes = [_P, C.c_int32]
 _lib.sbfem_read_state.argtypes = [_P, C.c_int32, _P, C.POINTER(C.c_int64), _P]
 _lib.sbfem_write_state.argtypes = [_P, _P, _P, C.c_int64, _P]
 _lib.sbfem_mesh_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
@@ -212,6 +213,10 @@ class Mesh:
 
     def step(self, n, stream=None):
         _check(_lib.sbfem_step_n(self.handle, int(n), _stream(stream)))
+
+    def set_graph_steps(self, steps):
+        """Replay whole chunks of `steps` steps from a captured HIP graph (0: launch each step)."""
+        _check(_lib.sbfem_set_graph_steps(self.handle, int(steps)))
 
     def read(self, which=0, stream=None):
         out = np.empty(self.n_dof, dtype=np.float64)

@@ -167,9 +167,11 @@ struct TileWork {
   int64_t tile;
 };
 
-// Launch description: either one mesh (single, work == nullptr) or a batch (refs + work
-// lists).  A step is two passes: the hanging-node cells (items [0, n_hang)), then every
-// owner tile (tiles [0, n_tiles)).  In a batch, TileWork::tile is the item or tile index.
+// Launch description: one mesh (work lists null; its ref is `single`, or refs[0] on the
+// device when refs is set) or a batch (refs + work lists).  A step is two passes: the
+// hanging-node cells (items [0, n_hang)), then every owner tile (tiles [0, n_tiles)).  In a
+// batch, TileWork::tile is the item or tile index.  Launches read step and parity of the
+// ref plus k; refs on the device (not `single`) let a captured graph replay at any step.
 struct TiledLaunch {
   MeshRef single;
   const MeshRef* refs = nullptr;
@@ -201,6 +203,9 @@ hipError_t launch_load(double* f, const int64_t* idx, const double* val, int64_t
 hipError_t launch_update(const double* un, double* unm1, double* f, const double* minv, int64_t ndof,
                          double dt2, double c, hipStream_t s);
 hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t s);
+// refs[0..n): step += steps, parity flipped when steps is odd (graph-safe: a kernel)
+hipError_t launch_refs_advance(MeshRef* refs, int32_t n, int64_t steps, hipStream_t s);
+hipError_t launch_ref_set(MeshRef* ref, const MeshRef& v, hipStream_t s);
 hipError_t launch_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s);
 hipError_t launch_finite32(const float* a, int64_t n, int32_t* flag, hipStream_t s);
 

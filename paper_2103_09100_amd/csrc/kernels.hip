@@ -117,23 +117,44 @@ hipError_t launch_finite32(const float* a, int64_t n, int32_t* flag, hipStream_t
 }
 
 hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& hook) {
-  const bool batch = L.refs != nullptr;
-  // hanging-node cells first: their rows land in the partial-force slots of the owner tiles
+  // hanging-node cells first: they store their row forces for the owner tiles
   if (L.n_hang > 0) {
     hook(2, true, s);
-    const TileWork* w = batch ? L.work_hang : nullptr;
     if (L.fp32)
-      (L.reduced ? tiled_hang_fp32r_launch : tiled_hang_fp32_launch)(L, w, 0, L.n_hang, s);
+      (L.reduced ? tiled_hang_fp32r_launch : tiled_hang_fp32_launch)(L, L.work_hang, 0, L.n_hang, s);
     else
-      (L.reduced ? tiled_hang_fp64r_launch : tiled_hang_fp64_launch)(L, w, 0, L.n_hang, s);
+      (L.reduced ? tiled_hang_fp64r_launch : tiled_hang_fp64_launch)(L, L.work_hang, 0, L.n_hang, s);
     hook(2, false, s);
   }
-  // then every owner tile: regular cells, the partial forces, the update
+  // then every owner tile: regular cells, the hanging-cell rows of its dofs, the update
   if (L.n_tiles > 0) {
     hook(1, true, s);
-    tiled_pure8_launch(L, batch ? L.work8 : nullptr, 0, L.n_tiles, s);
+    tiled_pure8_launch(L, L.work8, 0, L.n_tiles, s);
     hook(1, false, s);
   }
+  return hipGetLastError();
+}
+
+// Device mesh refs advanced by a number of steps (u and u_prev swap roles every step).
+__global__ void refs_advance_kernel(MeshRef* refs, int32_t n, int64_t steps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  MeshRef r = refs[i];
+  r.step += steps;
+  r.parity = (int32_t)((r.parity + steps) & 1);
+  refs[i] = r;
+}
+
+hipError_t launch_refs_advance(MeshRef* refs, int32_t n, int64_t steps, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(refs_advance_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, refs, n, steps);
+  return hipGetLastError();
+}
+
+__global__ void ref_set_kernel(MeshRef* ref, MeshRef v) { *ref = v; }
+
+hipError_t launch_ref_set(MeshRef* ref, const MeshRef& v, hipStream_t s) {
+  hipLaunchKernelGGL(ref_set_kernel, dim3(1), dim3(1), 0, s, ref, v);
   return hipGetLastError();
 }
 

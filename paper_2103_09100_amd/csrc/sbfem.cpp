@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -243,6 +244,10 @@ struct sbfem_mesh {
   int32_t block_threads_mixed = 256;  // owner tiles with larger cells
   bool walsh = true;
   int64_t layout[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // step loops captured in HIP graphs (owner-tile assembly): graph_steps per graph, 0 = off
+  int32_t graph_steps = 0;
+  sbfem::MeshRef* d_ref = nullptr;  // the mesh's ref on the device, read by graph replays
+  hipGraphExec_t gexec = nullptr;   // graph of graph_steps steps (built on first use)
 };
 
 namespace {
@@ -493,9 +498,54 @@ sbfem_status sbfem_critical_dt(const sbfem_patterns* p, const sbfem_mesh_desc* d
   return SBFEM_OK;
 }
 
+// Device work lists of a batch for one set of active meshes, and the graph of a chunk of
+// steps over them; kept between calls while graphs are on, so that a serving loop that
+// steps the same set repeatedly replays the same graph.
+struct BatchLists {
+  std::vector<sbfem_mesh*> meshes;  // active meshes; index = ref index
+  int32_t graph_steps = 0;
+  Allocator alloc;
+  sbfem::MeshRef* d_refs = nullptr;
+  sbfem::TileWork* d_w8 = nullptr;
+  sbfem::TileWork* d_wm = nullptr;
+  int64_t n8 = 0, nm = 0;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t stamp = 0;
+};
+static std::mutex g_batch_mu;  // guards the cache
+static std::vector<BatchLists*> g_batch_cache;
+static uint64_t g_batch_clock = 0;
+constexpr size_t kBatchCacheMax = 16;
+
+static void free_lists(BatchLists* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  dfree(b->alloc, b->d_refs);
+  dfree(b->alloc, b->d_w8);
+  dfree(b->alloc, b->d_wm);
+  delete b;
+}
+
+// drop every cached batch that steps this mesh (its graphs name the mesh's buffers)
+static void forget_batch_graphs(const sbfem_mesh* m) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (size_t i = 0; i < g_batch_cache.size();) {
+    const auto& v = g_batch_cache[i]->meshes;
+    if (std::find(v.begin(), v.end(), m) != v.end()) {
+      (void)hipDeviceSynchronize();
+      free_lists(g_batch_cache[i]);
+      g_batch_cache.erase(g_batch_cache.begin() + (std::ptrdiff_t)i);
+    } else {
+      ++i;
+    }
+  }
+}
+
 void sbfem_destroy_mesh(sbfem_mesh* m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
+  forget_batch_graphs(m);
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  dfree(m->alloc, m->d_ref);
   for (auto e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->flag_ev) (void)hipEventDestroy(m->flag_ev);
   if (m->flag_h) (void)hipHostFree(m->flag_h);
@@ -942,6 +992,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     ALLOC(hpairs, std::max<size_t>(1, hpairs.size()))
     ALLOC(hres, std::max<int64_t>(1, n_res))
     ALLOC(d_args, 2)
+    ALLOC(d_ref, 1)
     H2D(m->hitems, hitems.data(), hitems.size() * sizeof(sbfem::HangItem));
     H2D(m->hconn, hconn.data(), hconn.size() * 4);
     H2D(m->horient, hor.data(), hor.size());
@@ -1183,6 +1234,74 @@ static sbfem_status finish_steps(sbfem_mesh* m, hipStream_t s) {
   return SBFEM_OK;
 }
 
+// Graph of `steps` steps over the launch L whose refs live on the device (d_refs[0..n)):
+// launch k of the chunk reads step + k; a last kernel advances the refs by `steps`, so the
+// graph replays at whatever step the refs hold.  Captured on a private stream.
+static hipError_t capture_steps(sbfem::TiledLaunch L, sbfem::MeshRef* d_refs, int32_t n, int32_t steps,
+                                hipGraphExec_t* out) {
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    hipError_t le = hipSuccess;
+    for (int32_t k = 0; k < steps && le == hipSuccess; ++k) {
+      L.k = k;
+      le = sbfem::launch_tiled(L, cs);
+    }
+    if (le == hipSuccess) le = sbfem::launch_refs_advance(d_refs, n, steps, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);  // always ends the capture
+    if (e == hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  (void)hipStreamDestroy(cs);
+  return e;
+}
+
+static sbfem::MeshRef ref_of(const sbfem_mesh* m, int64_t ahead) {
+  sbfem::MeshRef r{};
+  r.args = m->d_args;
+  r.step = m->step + ahead;
+  r.parity = (int32_t)((tiled_parity(m) + ahead) & 1);
+  return r;
+}
+
+// Whole graphs of the mesh's step chunk; `left` keeps the steps still to take.
+static sbfem_status graph_steps_single(sbfem_mesh* m, int64_t& left, hipStream_t s) {
+  const int32_t G = m->graph_steps;
+  if (G <= 0 || m->assembly != SBFEM_ASM_TILED || m->profiling || left < G) return SBFEM_OK;
+  if (!m->gexec) {
+    sbfem::TiledLaunch L = tiled_launch(m, false);
+    L.refs = m->d_ref;
+    HIP_TRY(capture_steps(L, m->d_ref, 1, G, &m->gexec));
+  }
+  HIP_TRY(sbfem::launch_ref_set(m->d_ref, ref_of(m, 0), s));
+  for (; left >= G; left -= G) {
+    HIP_TRY(hipGraphLaunch(m->gexec, s));
+    m->step += G;
+    if (G & 1) std::swap(m->u, m->um1);
+  }
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_set_graph_steps(sbfem_mesh* m, int32_t steps) {
+  if (!m) return fail(SBFEM_EINVAL, "null mesh");
+  if (steps < 0 || steps > 4096) return fail(SBFEM_EINVAL, "graph steps must be in [0, 4096]");
+  if (steps > 0 && m->assembly != SBFEM_ASM_TILED) return fail(SBFEM_EINVAL, "step graphs need the owner-tile assembly");
+  if (steps == m->graph_steps) return SBFEM_OK;
+  HIP_TRY(hipSetDevice(m->device));
+  forget_batch_graphs(m);
+  if (m->gexec) {
+    HIP_TRY(hipDeviceSynchronize());  // the old graph may still run
+    (void)hipGraphExecDestroy(m->gexec);
+    m->gexec = nullptr;
+  }
+  m->graph_steps = steps;
+  return SBFEM_OK;
+}
+
 sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream) {
   if (!m) return fail(SBFEM_EINVAL, "null mesh");
   if (n_steps < 0) return fail(SBFEM_EINVAL, "negative step count");
@@ -1190,7 +1309,10 @@ sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream) {
   sbfem_status st = check_flag(m);
   if (st != SBFEM_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
-  for (int64_t k = 0; k < n_steps; ++k) {
+  int64_t left = n_steps;
+  st = graph_steps_single(m, left, s);
+  if (st != SBFEM_OK) return st;
+  for (int64_t k = 0; k < left; ++k) {
     st = enqueue_step(m, s);
     if (st != SBFEM_OK) return st;
   }
@@ -1199,74 +1321,126 @@ sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream) {
 }
 
 // Owner-tile meshes that share a pattern library and a product precision advance together:
-// one launch per step and tile class covers the tiles of every mesh that still has steps
-// to take (work lists rebuilt when a mesh finishes).  Other meshes step one by one.
+// one launch per step and pass covers the tiles of every mesh that still has steps to take
+// (a segment of steps per set of active meshes).  With graphs on (every mesh of the group
+// has graph_steps > 0; the smallest is used) the segment's whole chunks replay a cached
+// graph and the rest is launched directly.  Other meshes step one by one.
+static hipError_t build_lists(BatchLists* b, hipStream_t s) {
+  std::vector<sbfem::TileWork> w8, wm;
+  for (size_t i = 0; i < b->meshes.size(); ++i) {
+    const sbfem_mesh* m = b->meshes[i];
+    for (int64_t t = 0; t < m->n_pure8 + m->n_mixed; ++t) w8.push_back({(int32_t)i, 0, t});
+    for (int64_t t = 0; t < m->n_hang; ++t) wm.push_back({(int32_t)i, 0, t});
+  }
+  b->n8 = (int64_t)w8.size();
+  b->nm = (int64_t)wm.size();
+  hipError_t e = dalloc(b->alloc, &b->d_refs, b->meshes.size());
+  if (e == hipSuccess) e = dalloc(b->alloc, &b->d_w8, std::max<size_t>(1, w8.size()));
+  if (e == hipSuccess) e = dalloc(b->alloc, &b->d_wm, std::max<size_t>(1, wm.size()));
+  if (e == hipSuccess && !w8.empty())
+    e = hipMemcpyAsync(b->d_w8, w8.data(), w8.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !wm.empty())
+    e = hipMemcpyAsync(b->d_wm, wm.data(), wm.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host lists die here
+  return e;
+}
+
+// cached lists of this active set (the caller holds g_batch_mu); null on failure
+static BatchLists* cached_lists(const std::vector<sbfem_mesh*>& act, int32_t G, hipStream_t s, hipError_t& e) {
+  for (auto* b : g_batch_cache)
+    if (b->graph_steps == G && b->meshes == act) {
+      b->stamp = ++g_batch_clock;
+      return b;
+    }
+  if (g_batch_cache.size() >= kBatchCacheMax) {
+    e = hipStreamSynchronize(s);  // the least recently used entry may still be in flight
+    if (e != hipSuccess) return nullptr;
+    auto lru = std::min_element(g_batch_cache.begin(), g_batch_cache.end(),
+                                [](const BatchLists* x, const BatchLists* y) { return x->stamp < y->stamp; });
+    free_lists(*lru);
+    g_batch_cache.erase(lru);
+  }
+  auto* b = new BatchLists();
+  b->meshes = act;
+  b->graph_steps = G;
+  b->alloc = act[0]->alloc;
+  b->stamp = ++g_batch_clock;
+  e = build_lists(b, s);
+  if (e != hipSuccess) {
+    free_lists(b);
+    return nullptr;
+  }
+  g_batch_cache.push_back(b);
+  return b;
+}
+
 static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::vector<int64_t>& steps,
                                 hipStream_t s) {
   const size_t n = g.size();
-  std::vector<sbfem::MeshRef> refs(n);
+  int64_t most = 0;
+  int32_t G = g[0]->graph_steps;
   for (size_t i = 0; i < n; ++i) {
-    refs[i].args = g[i]->d_args;
-    refs[i].step = g[i]->step;
-    refs[i].parity = tiled_parity(g[i]);
-    refs[i].pad = 0;
-  }
-  int64_t tot8 = 0, totm = 0, most = 0;
-  for (size_t i = 0; i < n; ++i) {
-    tot8 += g[i]->n_pure8 + g[i]->n_mixed;
-    totm += g[i]->n_hang;
     most = std::max(most, steps[i]);
+    G = std::min(G, g[i]->graph_steps);
   }
-  sbfem::MeshRef* d_refs = nullptr;
-  sbfem::TileWork *d_w8 = nullptr, *d_wm = nullptr;
-  const Allocator& A = g[0]->alloc;
-  HIP_TRY(dalloc(A, &d_refs, n));
-  hipError_t e = dalloc(A, &d_w8, (size_t)std::max<int64_t>(1, tot8));
-  if (e == hipSuccess) e = dalloc(A, &d_wm, (size_t)std::max<int64_t>(1, totm));
-  if (e == hipSuccess) e = hipMemcpyAsync(d_refs, refs.data(), n * sizeof(sbfem::MeshRef), hipMemcpyHostToDevice, s);
-  std::vector<sbfem::TileWork> w8, wm;
-  std::vector<size_t> done(n, 0);
-  int64_t built_for = -1;
-  sbfem::TiledLaunch L = tiled_launch(g[0], false);
-  L.refs = d_refs;
-  L.work8 = d_w8;
-  L.work_hang = d_wm;
-  size_t lds = 0, lds_hang = 0;
+  sbfem::TiledLaunch L0 = tiled_launch(g[0], false);
   for (auto* m : g) {
-    lds = std::max(lds, (size_t)m->lds_bytes);
-    lds_hang = std::max(lds_hang, (size_t)m->lds_hang);
+    L0.lds = std::max(L0.lds, (size_t)m->lds_bytes);
+    L0.lds_hang = std::max(L0.lds_hang, (size_t)m->lds_hang);
   }
-  L.lds = lds;
-  L.lds_hang = lds_hang;
-  for (int64_t k = 0; k < most && e == hipSuccess; ++k) {
-    // active set changes only when a mesh runs out of steps
-    bool change = built_for < 0;
+  std::unique_lock<std::mutex> lk(g_batch_mu, std::defer_lock);
+  if (G > 0) lk.lock();
+  std::vector<std::vector<sbfem::MeshRef>> keep;  // host refs of the async copies
+  hipError_t e = hipSuccess;
+  for (int64_t k = 0; k < most && e == hipSuccess;) {
+    // the segment [k, end): meshes with steps left, until the first of them finishes
+    std::vector<sbfem_mesh*> act;
+    int64_t end = most;
     for (size_t i = 0; i < n; ++i)
-      if (steps[i] == k && k > 0) change = true;
-    if (change) {
-      if (built_for >= 0) e = hipStreamSynchronize(s);  // previous lists are in use until here
-      w8.clear();
-      wm.clear();
-      for (size_t i = 0; i < n; ++i) {
-        if (k >= steps[i]) continue;
-        for (int64_t t = 0; t < g[i]->n_pure8 + g[i]->n_mixed; ++t) w8.push_back({(int32_t)i, 0, t});
-        for (int64_t t = 0; t < g[i]->n_hang; ++t) wm.push_back({(int32_t)i, 0, t});
+      if (steps[i] > k) {
+        act.push_back(g[i]);
+        end = std::min(end, steps[i]);
       }
-      if (e == hipSuccess && !w8.empty())
-        e = hipMemcpyAsync(d_w8, w8.data(), w8.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
-      if (e == hipSuccess && !wm.empty())
-        e = hipMemcpyAsync(d_wm, wm.data(), wm.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
-      built_for = k;
+    BatchLists* b = nullptr;
+    if (G > 0) {
+      b = cached_lists(act, G, s, e);
+    } else {
+      b = new BatchLists();
+      b->meshes = act;
+      b->alloc = act[0]->alloc;
+      e = build_lists(b, s);
     }
-    L.k = k;
-    L.n_tiles = (int64_t)w8.size();
-    L.n_hang = (int64_t)wm.size();
-    if (e == hipSuccess) e = sbfem::launch_tiled(L, s);
+    if (e == hipSuccess) {
+      keep.emplace_back(act.size());
+      for (size_t j = 0; j < act.size(); ++j) keep.back()[j] = ref_of(act[j], k);
+      e = hipMemcpyAsync(b->d_refs, keep.back().data(), act.size() * sizeof(sbfem::MeshRef),
+                         hipMemcpyHostToDevice, s);
+    }
+    sbfem::TiledLaunch L = L0;
+    L.refs = b ? b->d_refs : nullptr;
+    L.work8 = b ? b->d_w8 : nullptr;
+    L.work_hang = b ? b->d_wm : nullptr;
+    L.n_tiles = b ? b->n8 : 0;
+    L.n_hang = b ? b->nm : 0;
+    int64_t j = k;
+    if (e == hipSuccess && G > 0 && end - k >= G) {
+      if (!b->gexec) e = capture_steps(L, b->d_refs, (int32_t)act.size(), G, &b->gexec);
+      for (; e == hipSuccess && end - j >= G; j += G) e = hipGraphLaunch(b->gexec, s);
+    }
+    const int64_t ref_k = j;  // the device refs now hold step offset ref_k
+    for (; e == hipSuccess && j < end; ++j) {
+      L.k = j - ref_k;
+      e = sbfem::launch_tiled(L, s);
+    }
+    if (G == 0 && b) {
+      const hipError_t q = hipStreamSynchronize(s);  // the lists are in use until here
+      if (e == hipSuccess) e = q;
+      free_lists(b);
+    }
+    k = end;
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dfree(A, d_refs);
-  dfree(A, d_w8);
-  dfree(A, d_wm);
+  if (lk.owns_lock()) lk.unlock();
   if (e != hipSuccess) return fail(SBFEM_EDEVICE, "batched step: %s", hipGetErrorString(e));
   for (size_t i = 0; i < n; ++i) {
     if (steps[i] & 1) std::swap(g[i]->u, g[i]->um1);

@@ -221,6 +221,8 @@ __device__ __forceinline__ bool block_unit(const MeshRef& single, const MeshRef*
     const TileWork w = load_const(as_const(work) + (first + t));
     r = load_const(as_const(refs) + w.mesh);
     ui = w.tile;
+  } else if (refs) {
+    r = load_const(as_const(refs));
   }
   // k steps after the step recorded in the mesh ref (batched calls advance every mesh together)
   step = r.step + k;

@@ -24,7 +24,7 @@ def device_patterns(nu, stream=None, workers=0):
 class Simulation:
     def __init__(self, mesh, dt=None, prod="fp64", state="fp64", assembly="tiled", orient_seed=None,
                  u0=None, v0=None, stream=None, workers=0, tile_nodes=0, block_threads=0,
-                 block_threads_mixed=0):
+                 block_threads_mixed=0, graph_steps=0):
         self.mesh = mesh
         self.patterns = device_patterns(mesh.nu, stream, workers)
         pid, code, conn = canonicalise(mesh, seed=orient_seed)
@@ -39,6 +39,8 @@ class Simulation:
         self.dt = float(dt)
         self.footprint = binding.footprint(self.patterns, desc)
         self.gpu = binding.Mesh(self.patterns, desc, keep, stream)
+        if graph_steps:
+            self.gpu.set_graph_steps(graph_steps)
         self.stream = stream
         self.n_dof = mesh.n_dof
 
