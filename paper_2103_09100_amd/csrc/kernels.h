@@ -106,6 +106,8 @@ struct TiledArgs {
   double dt2;
   double c;             // alpha dt / 2
   int32_t lds_bytes;    // dynamic LDS: 3 FP64 forces per owned node + 3 u values per local node
+  int64_t tile_nodes;   // tile t owns nodes [t tile_nodes, (t + 1) tile_nodes) (the last: up to the end)
+  int64_t halo_stride;  // > 0: the halo ids of tile t start at nodelist[t halo_stride], -1 padded
   int32_t block_threads;        // owner-tile pass: 64..512, multiple of 64
   int32_t block_threads_mixed;  // hanging-cell pass (one wave per item)
 };

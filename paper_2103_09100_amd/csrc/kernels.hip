@@ -171,23 +171,22 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 #undef SBFEM_L
 }
 
-// owner-tile pass
-void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
+// owner-tile pass: one block per tile (per (mesh, tile) in a batch)
+template <bool F, bool R>
+static void owner_pass(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
+  if (L.lds > 65536)
+    (void)hipFuncSetAttribute((const void*)tiled_step8<F, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds);
   const int64_t blocks = 8 * ((count + 7) / 8);
-#define SBFEM_L(F, R)                                                                                           \
-  do {                                                                                                          \
-    if (L.lds > 65536)                                                                                          \
-      (void)hipFuncSetAttribute((const void*)tiled_step8<F, R>, hipFuncAttributeMaxDynamicSharedMemorySize,      \
-                                (int)L.lds);                                                                    \
-    hipLaunchKernelGGL((tiled_step8<F, R>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, L.refs, \
-                       work, first, count, L.k, (int)L.force_only);                                             \
-  } while (0)
+  hipLaunchKernelGGL((tiled_step8<F, R>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, L.refs, work,
+                     first, count, L.k, (int)L.force_only);
+}
+
+void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
   if (L.fp32) {
-    if (L.reduced) SBFEM_L(true, true); else SBFEM_L(true, false);
+    if (L.reduced) owner_pass<true, true>(L, work, first, count, s); else owner_pass<true, false>(L, work, first, count, s);
   } else {
-    if (L.reduced) SBFEM_L(false, true); else SBFEM_L(false, false);
+    if (L.reduced) owner_pass<false, true>(L, work, first, count, s); else owner_pass<false, false>(L, work, first, count, s);
   }
-#undef SBFEM_L
 }
 
 }  // namespace sbfem

@@ -237,6 +237,7 @@ struct sbfem_mesh {
   int64_t n_hang = 0;
   int64_t lds_hang = 0;                 // LDS of a hanging-pass block (its pattern's matrix)
   int32_t tile_nodes = 0;
+  int64_t halo_stride = 0;              // tile halo lists at a fixed stride (0: packed)
   double* dWs64 = nullptr;              // Walsh blocks times s_e per scale class (pure 8-node tiles)
   float* dWs32 = nullptr;
   void* buf0 = nullptr;
@@ -631,6 +632,8 @@ static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const void* u, void*
   a.items = m->items;
   a.lidx = m->lidx;
   a.nodelist = m->nodelist;
+  a.tile_nodes = m->tile_nodes;
+  a.halo_stride = m->halo_stride;
   a.loads = m->tloads;
   a.matE = m->matE;
   a.h0 = m->h0;
@@ -961,7 +964,8 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     m->layout[0] = to.n_pure8;
     m->layout[1] = to.n_mixed;
     m->layout[2] = (int64_t)to.items.size();
-    m->layout[3] = (int64_t)to.nodelist.size() + N;
+    m->layout[3] = to.local_entries;
+    m->halo_stride = to.halo_stride;
     m->layout[4] = (int64_t)hcells.size();  // regular cell entries over all tiles, plus the hanging cells
     for (const auto& it : to.items) m->layout[4] += it.count;
     m->layout[5] = to.tile_nodes;

@@ -311,6 +311,59 @@ __device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& 
   for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0;
 }
 
+// The same staging with every global load issued up front, for tiles whose owned nodes fit
+// one per thread and whose other local nodes two per thread: the caller has loaded the
+// thread's halo node ids (h0 = halo entry tid, h1 = entry tid + nt, -1 if none) as its
+// first loads, so a tile costs two dependent round trips to memory (ids, then u), not two
+// per node a thread stages.  In two halves (loads, then LDS stores) so that the caller can
+// request its first cell record in between.
+struct StagedNodes {
+  double r[3], vo[3], v0[3], v1[3];
+};
+
+template <bool FP32, bool RED>
+__device__ __forceinline__ StagedNodes stage_loads(const TiledArgs& a, int64_t own0, int n_own, int32_t h0,
+                                                   int32_t h1, int tid) {
+  const int32_t sm = state_of<RED>(a);
+  StagedNodes v{};
+  if constexpr (FP32) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v.r[c] = state_load(a.u, sm, a.ndof, 3 * own0 + c);
+  }
+  if (tid < n_own) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v.vo[c] = state_load(a.u, sm, a.ndof, 3 * (own0 + tid) + c);
+  }
+  if (h0 >= 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v.v0[c] = state_load(a.u, sm, a.ndof, 3 * (int64_t)h0 + c);
+  }
+  if (h1 >= 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v.v1[c] = state_load(a.u, sm, a.ndof, 3 * (int64_t)h1 + c);
+  }
+  return v;
+}
+
+template <bool FP32>
+__device__ __forceinline__ void stage_stores(const StagedNodes& v, int n_own, int32_t h0, int32_t h1,
+                                             typename LdsType<FP32>::T* ul, double* fl, int tid, int nt) {
+  auto put = [&](int l, double x, double y, double z) {
+    if constexpr (FP32) {
+      reinterpret_cast<float4*>(ul)[l] =
+          make_float4((float)(x - v.r[0]), (float)(y - v.r[1]), (float)(z - v.r[2]), 0.0f);
+    } else {
+      ul[3 * l + 0] = x;
+      ul[3 * l + 1] = y;
+      ul[3 * l + 2] = z;
+    }
+  };
+  if (tid < n_own) put(tid, v.vo[0], v.vo[1], v.vo[2]);
+  if (h0 >= 0) put(n_own + tid, v.v0[0], v.v0[1], v.v0[2]);
+  if (h1 >= 0) put(n_own + nt + tid, v.v1[0], v.v1[1], v.v1[2]);
+  for (int i = tid; i < 3 * n_own; i += nt) fl[i] = 0;
+}
+
 // Hanging-node cell of NN nodes in the hanging-cell pass: u_e gathered from global memory,
 // oriented, 16-bit operands if asked, dense master product over all rows scaled by s_e;
 // row i of the item's lane goes to hres[res0 + 64 i + lane] (the owner tiles add it).
@@ -429,33 +482,28 @@ __global__ void __launch_bounds__(512, FP32 ? 4 : 1) tiled_hang(MeshRef single, 
 #undef SBFEM_TCASE
 }
 
-// Owner-tile pass over every tile.  Loads whose addresses are known at the start are issued
-// before the staging so that their latency overlaps it: the wave's first cell record and,
-// with FP64 state, the update operands of the thread's owned dofs (at most 3 per thread).
+// One owner tile (steps 1-4 of the pass).  own0 and n_own come from the tile index and the
+// tile size, so that the loads that need nothing else (the update operands of the thread's
+// owned dofs, at most 3 per thread with FP64 state, and with `ids` the staging of the owned
+// nodes and of the halo nodes h0, h1) are issued while the tile record is still on its way;
+// the record feeds the item loop, the loads and the hanging-cell forces.
 template <bool FP32, bool RED>
-__global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
-                                                   const TileWork* __restrict__ work, int64_t first,
-                                                   int64_t count, int64_t k, int force_only) {
+__device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& tile, int64_t own0, int n_own,
+                                           int64_t step, int force_only, bool ids, int32_t h0, int32_t h1,
+                                           double* lds) {
   using T = typename LdsType<FP32>::T;
-  extern __shared__ double lds[];
-  TiledArgs a;
-  int64_t ti, step;
-  if (!block_unit(single, refs, work, first, count, k, xcd_unit(count), a, ti, step)) return;
-  const OwnerTile tile = load_const(as_const(a.tiles) + ti);
-  const int n_own = tile.n_own;
   double* fl = lds;
   T* ul = (T*)(lds + 3 * (int64_t)n_own);
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int n_waves = nt >> 6;
-  cptr_t<CellItem> items = as_const(a.items) + tile.item0;
   constexpr int kPre = 3;
   const int n_dof = 3 * n_own;
   const bool pre = !RED && !force_only && n_dof <= kPre * nt;
   double pu[kPre], pp[kPre], pm[kPre];
   if (pre) {
-    const int64_t d0 = 3 * tile.own0;
+    const int64_t d0 = 3 * own0;
     const gptr_t<double> u = as_global((const double*)a.u), up = as_global((const double*)a.um1),
                          mi = as_global((const double*)a.minv);
 #pragma unroll
@@ -469,6 +517,9 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
       }
     }
   }
+  StagedNodes sv{};
+  if (ids) sv = stage_loads<FP32, RED>(a, own0, n_own, h0, h1, tid);
+  cptr_t<CellItem> items = as_const(a.items) + tile.item0;
   int w = wave;
   CellItem it{};
   uint4 q = make_uint4(0, 0, 0, 0);
@@ -476,7 +527,10 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
     it = load_const(items + w);
     if (lane < it.count) q = cell8_record(a, it, lane);
   }
-  tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
+  if (ids)
+    stage_stores<FP32>(sv, n_own, h0, h1, ul, fl, tid, nt);
+  else
+    tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
   tile_hang_forces(a, tile, fl, tid, nt);
@@ -496,7 +550,7 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   }
   __syncthreads();
   if (pre) {
-    const int64_t d0 = 3 * tile.own0;
+    const int64_t d0 = 3 * own0;
     const gmut_t<double> up = as_global_mut((double*)a.um1);
     const double inv = 1.0 / (1.0 + a.c);
 #pragma unroll
@@ -511,6 +565,33 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
   } else {
     tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
   }
+}
+
+// Owner-tile pass, one block per work unit (a tile; in a batched launch a (mesh, tile)).
+// With halo lists at a fixed stride and tiles that fit the block (owned nodes one per
+// thread, halo nodes two per thread), the halo ids are the block's first loads.
+template <bool FP32, bool RED>
+__global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
+                                                   const TileWork* __restrict__ work, int64_t first,
+                                                   int64_t count, int64_t k, int force_only) {
+  extern __shared__ double lds[];
+  TiledArgs a;
+  int64_t ti, step;
+  if (!block_unit(single, refs, work, first, count, k, xcd_unit(count), a, ti, step)) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t own0 = ti * a.tile_nodes;
+  const int64_t n_nodes = a.ndof / 3;
+  const int n_own = (int)(n_nodes - own0 < a.tile_nodes ? n_nodes - own0 : a.tile_nodes);
+  const int64_t H = a.halo_stride;
+  const bool ids = H > 0 && n_own <= nt && H <= 2 * nt;
+  int32_t h0 = -1, h1 = -1;
+  if (ids) {
+    const gptr_t<int32_t> nl = as_global(a.nodelist) + ti * H;
+    if (tid < H) h0 = nl[tid];
+    if (tid + nt < H) h1 = nl[tid + nt];
+  }
+  const OwnerTile tile = load_const(as_const(a.tiles) + ti);
+  owner_tile<FP32, RED>(a, tile, own0, n_own, step, force_only, ids, h0, h1, lds);
 }
 
 }  // namespace sbfem

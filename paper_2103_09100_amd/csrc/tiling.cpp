@@ -154,14 +154,26 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
       }
   });
 
-  // concatenate in tile order
+  // concatenate in tile order.  Halo lists at a fixed stride (the largest halo) when the
+  // padding costs at most half the lists again: then a block finds its halo ids from its
+  // tile index alone, without waiting for the tile record.
   out.tile_nodes = tile_nodes;
+  int64_t halo_max = 0, halo_sum = 0;
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    const int64_t n_own = std::min<int64_t>(tile_nodes, N - t * tile_nodes);
+    const int64_t h = (int64_t)res[t].local.size() - n_own;
+    halo_max = std::max(halo_max, h);
+    halo_sum += h;
+  }
+  const int64_t stride = std::max<int64_t>(1, halo_max);
+  out.halo_stride = n_tiles * stride <= halo_sum + halo_sum / 2 + (1 << 20) ? stride : 0;
+  out.local_entries = halo_sum + N;
   for (int64_t t = 0; t < n_tiles; ++t) {
     TileOut& r = res[t];
     OwnerTile ot{};
     ot.own0 = t * tile_nodes;
     ot.n_own = (int32_t)std::min<int64_t>(tile_nodes, N - ot.own0);
-    ot.node0 = (int64_t)out.nodelist.size();
+    ot.node0 = out.halo_stride ? t * out.halo_stride : (int64_t)out.nodelist.size();
     ot.n_local = (int32_t)r.local.size();
     ot.item0 = (int64_t)out.items.size();
     ot.n_items = (int32_t)r.items.size();
@@ -176,6 +188,7 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
     }
     // owned nodes are implicit (own0 + i); only the others are listed
     out.nodelist.insert(out.nodelist.end(), r.local.begin() + ot.n_own, r.local.end());
+    if (out.halo_stride) out.nodelist.resize((size_t)((t + 1) * out.halo_stride), -1);
     out.lidx.insert(out.lidx.end(), r.lidx.begin(), r.lidx.end());
     out.loads.insert(out.loads.end(), r.loads.begin(), r.loads.end());
     out.tiles.push_back(ot);

@@ -31,7 +31,9 @@ struct TilingOutput {
   int64_t n_pure8 = 0, n_mixed = 0;
   int64_t max_local = 0;
   std::vector<CellItem> items;
-  std::vector<int32_t> nodelist;
+  std::vector<int32_t> nodelist;       // halo node ids per tile (at halo_stride, -1 padded, if > 0)
+  int64_t halo_stride = 0;
+  int64_t local_entries = 0;           // local nodes over all tiles
   std::vector<uint16_t> lidx;
   std::vector<LoadEntry> loads;
   // scale classes of the pure 8-node tiles: key = level * 256 + material, in order of first use;
