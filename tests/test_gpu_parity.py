@@ -305,3 +305,24 @@ def test_autotuned_shape_gives_the_same_result(sim_mod):
     s = sim_mod.Simulation(m, prod="fp64", tile_nodes=tn, block_threads=bt, block_threads_mixed=btm)
     s.step(50)
     assert np.abs(s.u() - ref.u()).max() <= 1e-12 * np.abs(ref.u()).max()
+
+
+@pytest.mark.parametrize("shape", [(1024, 512, 256), (512, 256, 128), (64, 64, 64), (128, 512, 512)])
+@pytest.mark.parametrize("prod", ["fp64", "fp32"])
+def test_tile_shapes_agree(sim_mod, prod, shape):
+    """Owner-tile shapes that take the generic staging (owned nodes beyond one per thread, or
+    halo nodes beyond two per thread) or the up-front staging agree with the default shape:
+    FP64 to rounding, FP32 products to the mixed-path bound (each tile rounds u relative to
+    its own first owned node, so different tiles round differently)."""
+    m = configs.small_zoo()
+    tn, bt, btm = shape
+    _say(f"[tile shape {shape} {prod}]")
+    ref = sim_mod.Simulation(m, prod=prod)
+    ref.step(60)
+    s = sim_mod.Simulation(m, prod=prod, tile_nodes=tn, block_threads=bt, block_threads_mixed=btm)
+    s.step(60)
+    lay = s.gpu.layout()
+    assert lay["tile_nodes"] <= tn
+    err = np.abs(s.u() - ref.u()).max() / np.abs(ref.u()).max()
+    _say(f"  tile_nodes {lay['tile_nodes']}, max local {lay['max_local_nodes']}: {err:.3e}")
+    assert err <= (1e-12 if prod == "fp64" else 1e-5)
