@@ -2,17 +2,17 @@
 //
 // Nodes carry internal ids in first-touch order along the cell sequence, so a
 // run of consecutive ids is a spatially compact set.  Tile t owns the ids
-// [t*T, (t+1)*T).  Its work is every cell that touches an owned node; for each
-// such cell only the rows of owned nodes are accumulated.  Cells are grouped
-// into wave-sized items of one pattern and one row mask so that the master
-// matrix and the row selection are uniform within a wave.
+// [t*T, (t+1)*T).  Its work is every regular 8-node cell (pattern p8, identity
+// orientation) that touches an owned node; for each such cell only the rows of
+// owned corners are accumulated.  Hanging-node cells are not staged here: they
+// have a pass of their own, whose rows reach the owning tiles as (dof, result)
+// pairs (set up with the mesh).
 //
-// Regular 8-node cells (pattern p8, identity orientation) form the items:
-// one scale class (level, material) per item so the pre-scaled Walsh table is
-// uniform in a wave, full waves of cells in cell (Morton) order (the item's
-// mask is the union of the cells' owned-corner masks), and the eight local node
-// indices of a cell stored together (16 bytes, lane-major).  Tiles with only such cells run
-// the dedicated 8-node kernel.
+// The regular cells form the items: one scale class (level, material) per item
+// so the pre-scaled Walsh table is uniform in a wave, full waves of cells in
+// cell (Morton) order (the item's mask is the union of the cells' owned-corner
+// masks), and the eight local node indices of a cell stored together (16 bytes,
+// lane-major).
 #include <algorithm>
 #include <thread>
 #include <unordered_map>
