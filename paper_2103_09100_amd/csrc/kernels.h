@@ -194,7 +194,7 @@ hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& h
 void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, bool atomic, hipStream_t s);
 void ebe_mixed_fp64_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
 void ebe_mixed_fp32_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
-void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void owner_pass_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_hang_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_hang_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_hang_fp64r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);

@@ -129,7 +129,7 @@ hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& h
   // then every owner tile: regular cells, the hanging-cell rows of its dofs, the update
   if (L.n_tiles > 0) {
     hook(1, true, s);
-    tiled_pure8_launch(L, L.work8, 0, L.n_tiles, s);
+    owner_pass_launch(L, L.work8, 0, L.n_tiles, s);
     hook(1, false, s);
   }
   return hipGetLastError();
@@ -181,7 +181,7 @@ static void owner_pass(const TiledLaunch& L, const TileWork* work, int64_t first
                      first, count, L.k, (int)L.force_only);
 }
 
-void tiled_pure8_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
+void owner_pass_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
   if (L.fp32) {
     if (L.reduced) owner_pass<true, true>(L, work, first, count, s); else owner_pass<true, false>(L, work, first, count, s);
   } else {
