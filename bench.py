@@ -348,6 +348,30 @@ def precision_sweep(torch, args):
                 steps=n_total, snapshot_every=every, load_ends_at_step=t_end, energy_steps=h_at, rows=rows)
 
 
+def copy_bandwidth(torch, stream, n_bytes=1 << 30, reps=10):
+    """HBM bandwidth of a plain copy on this GPU (read n_bytes, write n_bytes), the faster of
+    the runtime's device copy and an elementwise kernel (y = 1 * x): the practical ceiling
+    that the roofline fraction is also quoted against."""
+    x = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    best = 0.0
+    for op in (lambda: y.copy_(x), lambda: torch.mul(x, 1.0, out=y)):
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                op()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                op()
+            b.record(stream)
+        torch.cuda.synchronize()
+        best = max(best, 2 * n_bytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9)
+    del x, y
+    torch.cuda.empty_cache()
+    return best
+
+
 def small_mesh_latency(torch, steps=1000, graph_steps=50, prods=("fp64", "fp32")):
     """Per-step time of the 2187-dof cube (launch-bound): steps launched one by one vs
     replayed from a graph of `graph_steps` steps; the two final states are compared."""
@@ -452,6 +476,8 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy probe: 3 x (read 1 GiB, write 1 GiB) elementwise kernel")
         del x, y
+    copy_gbs = copy_bandwidth(torch, stream)
+    log(f"[bench] plain copy on this GPU: {copy_gbs:.0f} GB/s")
     results = {}
     finals = {}
     plan = [(m, args.steps, args.warmup) for m in args.modes.split(",") if m]
@@ -505,6 +531,7 @@ def main():
                      "traffic": traffic,
                      "step_achieved": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9,
                      "step_frac": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "alg_bytes_per_launch": alg8, "alg_bytes_other_kernel": lay["alg_bytes_other"],
                      "alg_bytes_per_step": ab["step"], "avg_launch_ms": k8["ms_avg"],
                      "launches": k8["launches"]},
