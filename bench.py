@@ -251,7 +251,8 @@ def serving(torch, args):
         for r in reqs:
             r.reset()
         srv = Server(budget_bytes=budget, quantum=args.serve_quantum, prod=args.serve_prod,
-                     stream=st.cuda_stream, setup_stream=st2.cuda_stream, shapes=shapes)
+                     stream=st.cuda_stream, setup_stream=st2.cuda_stream, shapes=shapes,
+                     graph_steps=args.serve_graph_steps)
         t1 = time.time()
         srv.run(reqs)
         stats = latency_stats(reqs)
@@ -277,6 +278,7 @@ def serving(torch, args):
                                          ms_per_step={str(list(c)): round(ms, 4) for c, ms in shapes.tables[b]})
                           for b in sorted(shapes.shapes)}
     out.update(requests=len(reqs), product=args.serve_prod, state="fp64", quantum=args.serve_quantum,
+               graph_steps=args.serve_graph_steps,
                dof_steps=float(total), alone_vs_served_max_rel=worst, alone_checked=[int(i) for i in pick],
                workload="Poisson stream (20/s) of seeded inclusion octrees, 1e4-5e6 dofs log-uniform, "
                         "200-3000 steps, built before the clock")
@@ -419,6 +421,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-quantum", type=int, default=50, help="steps per batched call")
     ap.add_argument("--serve-prod", default="fp32")
+    ap.add_argument("--serve-graph-steps", type=int, default=0,
+                    help="replay the batched steps of the serving loop from cached HIP graphs of this many steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for the HBM byte counters)")
     ap.add_argument("--sweep", action="store_true",

@@ -52,8 +52,9 @@ class Server:
     own stream so it overlaps the stepping of the admitted simulations."""
 
     def __init__(self, budget_bytes=4 << 30, quantum=50, prod="fp32", stream=None, setup_stream=None,
-                 clock=time.perf_counter, shapes=None):
+                 clock=time.perf_counter, shapes=None, graph_steps=0):
         self.budget = int(budget_bytes)
+        self.graph_steps = int(graph_steps)  # > 0: batched steps replayed from cached HIP graphs
         self.quantum = int(quantum)
         self.prod = prod
         self.shapes = shapes      # owner-tile shape per mesh: an object with .shape(mesh) (autotune.ShapeCache)
@@ -105,6 +106,8 @@ class Server:
                     else:
                         pats, desc, keep, fp = r.extra.pop("prep")
                         r.extra["gpu"] = binding.Mesh(pats, desc, keep, self.setup_stream)
+                        if self.graph_steps:
+                            r.extra["gpu"].set_graph_steps(self.graph_steps)
                         with lock:
                             created.append(r)
                 except Exception as exc:   # surfaced by the main loop
