@@ -403,6 +403,28 @@ def small_mesh_latency(torch, steps=1000, graph_steps=50, prods=("fp64", "fp32")
     return out
 
 
+def cache_resident_mesh(torch, steps=500):
+    """The 2e6-dof all-pattern mesh (it fits the 256 MB last-level cache): time per step and
+    DOF-steps/s of the FP32 and FP64 paths, with their final states compared."""
+    from meshgen import configs
+    from paper_2103_09100_amd.solver import Simulation
+    stream = torch.cuda.Stream()
+    m = configs.cfg2()
+    out = {"workload": f"cfg2: sphere-band octree L3/7 with every cell pattern, {m.n_dof} dofs, {m.n_cells} cells",
+           "steps": steps}
+    finals = {}
+    for prod in ("fp32", "fp64"):
+        sim = Simulation(m, prod=prod, assembly="tiled", stream=stream.cuda_stream)
+        ms, _ = time_mode(sim, torch, stream, steps, 10)
+        finals[prod] = sim.u()
+        out[prod] = {"ms_per_step": ms, "dof_steps_per_s": m.n_dof / (ms * 1e-3)}
+        sim.close()
+        log(f"[bench] cfg2 {prod}: {ms * 1e3:.1f} us/step, {m.n_dof / (ms * 1e-3):.3e} DOF-steps/s")
+    out["rel_err_fp32_vs_fp64"] = float(np.abs(finals["fp32"] - finals["fp64"]).max() /
+                                        max(np.abs(finals["fp64"]).max(), 1e-300))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +438,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--small", type=int, default=1000, help="steps of the small-mesh latency check (0: skip)")
+    ap.add_argument("--mid", type=int, default=500, help="steps of the cache-resident 2e6-dof mesh (0: skip)")
     ap.add_argument("--graph-steps", type=int, default=50, help="steps per captured graph")
     ap.add_argument("--serve-only", action="store_true", help="only the serving stream")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
@@ -550,6 +573,8 @@ def main():
         out["rel_err_vs_fp64"] = float(np.abs(finals[head] - ref).max() / np.abs(ref).max())
     if args.small > 0:
         out["small_mesh_step_us"] = small_mesh_latency(torch, args.small, args.graph_steps)
+    if args.mid > 0:
+        out["cache_resident_mesh"] = cache_resident_mesh(torch, args.mid)
     if args.serve > 0:
         out["serving"] = serving(torch, args)
         out["p99_latency_s"] = out["serving"]["budget"]["p99_s"]
