@@ -48,8 +48,10 @@ typedef enum { SBFEM_STATE_FP64 = 0, SBFEM_STATE_FP32 = 1, SBFEM_STATE_KAHAN32 =
  *  ATOMIC  element forces scattered with floating-point atomics, separate update pass;
  *  COLOUR  cells processed colour by colour (no two cells of a colour share a node),
  *          plain read-modify-write, bitwise reproducible, separate update pass;
- *  TILED   owner tiles: each block owns a run of nodes, sums the rows of every cell
- *          touching them in on-chip memory and updates them in the same pass.
+ *  TILED   owner tiles: each block owns a run of nodes, sums the rows of every regular
+ *          8-node cell touching them in on-chip memory and updates them in the same
+ *          pass; the hanging-node cells are computed once each in a pass before it,
+ *          whose row forces the owning blocks add (no atomics outside on-chip memory).
  */
 typedef enum { SBFEM_ASM_ATOMIC = 0, SBFEM_ASM_COLOUR = 1, SBFEM_ASM_TILED = 2 } sbfem_asm;
 /* Load-time function P(t) (Sec. 5, eqs. Ricker, Triangle, Lamb). */
@@ -147,10 +149,12 @@ sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream);
 
 /*
  * Advance several meshes in one stream: mesh i takes n_steps[i] steps (a mesh
- * may appear once).  Owner-tile meshes that share a pattern library, product
- * precision and block shape advance together: each launch covers the tiles of
- * every such mesh that still has steps to take.  Other meshes are stepped in
- * turn.  Returns after the work of the batched groups has completed.
+ * may appear once; n_steps[i] >= 0).  Owner-tile meshes that share a pattern
+ * library, product precision, state storage and block shape advance together:
+ * each launch covers the tiles (and hanging-cell items) of every such mesh that
+ * still has steps to take.  Other meshes are stepped in turn.  Returns after the
+ * work of the batched groups has completed.  A repeated mesh or a negative count:
+ * SBFEM_EINVAL, nothing stepped.
  */
 sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream);
 
