@@ -115,3 +115,26 @@ def test_graph_steps_rejected_outside_range(sim_mod):
     c = sim_mod.Simulation(m, assembly="colour")
     with pytest.raises(binding.SbfemError):
         c.gpu.set_graph_steps(8)
+
+
+def test_graphs_step_directly_while_profiling_and_take_the_smallest_chunk(sim_mod):
+    from paper_2103_09100_amd import binding
+    m = configs.small_zoo()
+    g = sim_mod.Simulation(m, prod="fp64", assembly="tiled", graph_steps=6)
+    d = sim_mod.Simulation(m, prod="fp64", assembly="tiled")
+    # profiling records an event pair per launch: the steps are launched one by one
+    g.gpu.profile(True)
+    g.step(12)
+    prof = g.gpu.profile_read()
+    g.gpu.profile(False)
+    assert prof["element_8node"][1] == 12 and prof["element_larger"][1] == 12
+    d.step(12)
+    assert _rel(g.u(), d.u()) <= TOL
+    # a batch of meshes with different chunk lengths replays chunks of the smallest
+    h = sim_mod.Simulation(configs.cfg1(), prod="fp64", assembly="tiled", graph_steps=4)
+    e = sim_mod.Simulation(configs.cfg1(), prod="fp64", assembly="tiled")
+    binding.step_batch([g.gpu, h.gpu], [10, 10])
+    d.step(10)
+    e.step(10)
+    assert g.gpu.read(0)[1] == 22 and h.gpu.read(0)[1] == 10
+    assert _rel(g.u(), d.u()) <= TOL and _rel(h.u(), e.u()) <= TOL
