@@ -425,6 +425,29 @@ def cache_resident_mesh(torch, steps=500):
     return out
 
 
+def accuracy_run(torch, mesh, steps, every=250):
+    """FP32 products against FP64 products (both FP64 state) on one mesh over `steps` steps:
+    e_max = max over the sampled steps of |u32 - u64|_inf / max over the same steps of
+    |u64|_inf (the error measure of the mixed path's target)."""
+    from paper_2103_09100_amd.solver import Simulation
+    stream = torch.cuda.Stream()
+    sims = {p: Simulation(mesh, prod=p, assembly="tiled", stream=stream.cuda_stream) for p in ("fp32", "fp64")}
+    num, den, done, samples = 0.0, 0.0, 0, []
+    while done < steps:
+        k = min(every, steps - done)
+        for sim in sims.values():
+            sim.step(k)
+        done += k
+        u32, u64 = sims["fp32"].u(), sims["fp64"].u()
+        d, r = float(np.abs(u32 - u64).max()), float(np.abs(u64).max())
+        num, den = max(num, d), max(den, r)
+        samples.append({"step": done, "diff_inf": d, "ref_inf": r})
+        log(f"[accuracy] step {done}: |u32 - u64| {d:.3e}, |u64| {r:.3e}")
+    for sim in sims.values():
+        sim.close()
+    return {"steps": steps, "every": every, "e_max": num / den if den else 0.0, "samples": samples}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,6 +462,8 @@ def main():
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--small", type=int, default=1000, help="steps of the small-mesh latency check (0: skip)")
     ap.add_argument("--mid", type=int, default=500, help="steps of the cache-resident 2e6-dof mesh (0: skip)")
+    ap.add_argument("--accuracy-steps", type=int, default=0,
+                    help="only compare FP32 with FP64 products on the bench mesh over this many steps")
     ap.add_argument("--graph-steps", type=int, default=50, help="steps per captured graph")
     ap.add_argument("--serve-only", action="store_true", help="only the serving stream")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
@@ -491,6 +516,13 @@ def main():
     mesh, desc = make_mesh(args.config)
     log(f"[bench] mesh {args.config}: {mesh.n_cells} cells, {mesh.n_nodes} nodes, {mesh.n_dof} dofs "
         f"({time.time() - t0:.0f} s)")
+    if args.accuracy_steps > 0:
+        acc = accuracy_run(torch, mesh, args.accuracy_steps)
+        print(json.dumps({"metric": "max relative displacement difference, FP32 vs FP64 products (FP64 state)",
+                          "value": acc["e_max"], "unit": "relative", "n_gpus": 1, "higher_is_better": False,
+                          "data": "synthetic", "config": {"workload": f"{args.config}: {desc}"},
+                          "accuracy": acc}), flush=True)
+        return
     ab = dict(step=algorithmic_bytes(mesh))
     log(f"[bench] algorithmic bytes/step {ab['step'] / 1e9:.3f} GB ({ab['step'] / mesh.n_dof:.1f} B/dof)")
 
