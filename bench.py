@@ -491,8 +491,8 @@ def main():
         summarise_trace(*args.summarise_trace, header=args.summary_header)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              f"path is not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "
+              f"(one process per GPU with a halo exchange) is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
