@@ -45,10 +45,43 @@ def log(*a):
 
 
 def algorithmic_bytes(mesh):
-    """Bytes the method must move per step: per dof u_n, u_{n-1}, M^-1 read and u_{n+1}
-    written (8 B each); per cell its node ids (4 B each) and orientation, level, material
-    (1 B each); per load entry index + value (16 B)."""
+    """Bytes per step under the per-dof model (FP64 state, FP64 inverse mass per dof): per dof
+    u_n, u_{n-1}, M^-1 read and u_{n+1} written (8 B each); per cell its node ids (4 B each)
+    and orientation, level, material (1 B each); per load entry index + value (16 B).  The
+    library reports the bytes of its own storage (inverse mass per node) per pass."""
     return 32 * mesh.n_dof + 4 * int(mesh.conn.shape[0]) + 3 * mesh.n_cells + 16 * len(mesh.load_dof)
+
+
+def owner_kernel_name(prod, state="fp64"):
+    """rocprofv3's short name of the owner-tile kernel instance for a product / state form."""
+    from paper_2103_09100_amd.binding import PROD, STATE
+    return f"tiled_step8<{PROD[prod]}, {STATE[state]}>"
+
+
+def hang_kernel_name(prod, state="fp64"):
+    from paper_2103_09100_amd.binding import PROD, STATE
+    return f"tiled_hang_mma<{PROD[prod]}, {STATE[state]}>"
+
+
+def roofline_block(r, copy_gbs, prod, state="fp64"):
+    """Roofline of the owner-tile kernel (the dominant one) and of the whole step, from the
+    library's algorithmic bytes per pass and the per-launch HIP events of the timed region."""
+    k8 = r["kernels"]["element_8node"]
+    kh = r["kernels"]["element_larger"]
+    lay = r["layout"]
+    alg8, algo = lay["alg_bytes_8node"], lay["alg_bytes_other"]
+    achieved = alg8 / (k8["ms_avg"] * 1e-3) / 1e9 if k8["ms_avg"] > 0 else 0.0
+    step_bytes = alg8 + algo
+    kname = owner_kernel_name(prod, state)
+    return {"bound": "hbm", "kernel": f"{kname}: owner-tile pass (regular 8-node cells, hanging-cell row forces, update)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": counter_traffic(kname),
+            "step_achieved": step_bytes / (r["ms_per_step"] * 1e-3) / 1e9,
+            "step_frac": step_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
+            "alg_bytes_per_launch": alg8, "alg_bytes_other_kernel": algo, "alg_bytes_per_step": step_bytes,
+            "avg_launch_ms": k8["ms_avg"], "launches": k8["launches"],
+            "hang_kernel": hang_kernel_name(prod, state), "hang_avg_launch_ms": kh["ms_avg"]}
 
 
 def kernel_sources_hash():
@@ -448,6 +481,51 @@ def accuracy_run(torch, mesh, steps, every=250):
     return {"steps": steps, "every": every, "e_max": num / den if den else 0.0, "samples": samples}
 
 
+def run_modes(torch, mesh, plan, stream, label="bench"):
+    """Create, time and read back each (prod:assembly, steps, warm-up) of the plan in turn."""
+    from paper_2103_09100_amd.solver import Simulation
+    results, finals = {}, {}
+    for mode, n_steps, n_warm in plan:
+        prod, assembly = mode.split(":")
+        t1 = time.time()
+        sim = Simulation(mesh, prod=prod, assembly=assembly, stream=stream.cuda_stream)
+        info = sim.gpu.info()
+        log(f"[{label}] {mode}: created in {time.time() - t1:.0f} s, dt={sim.dt:.4e}, "
+            f"{info['n_colours']} colours, {info['device_bytes'] / 1e9:.1f} GB, layout {sim.gpu.layout()}")
+        ms, prof = time_mode(sim, torch, stream, n_steps, n_warm)
+        finals[mode] = sim.u()
+        results[mode] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), kernels=prof, steps=n_steps,
+                             layout=sim.gpu.layout())
+        log(f"[{label}] {mode}: {ms:.3f} ms/step, {results[mode]['value']:.3e} DOF-steps/s, "
+            + ", ".join(f"{k} {v['ms_avg']:.3f} ms x{v['launches']}" for k, v in prof.items()))
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return results, finals
+
+
+def pattern_rich(torch, stream, copy_gbs, steps, warmup):
+    """The 2.07e7-dof sphere-band mesh (1.3 % hanging-node cells, every pattern): throughput
+    and roofline of the FP32 and FP64 paths."""
+    from meshgen import configs
+    mesh = configs.cfg4()
+    log(f"[cfg4] mesh: {mesh.n_cells} cells, {mesh.n_dof} dofs, "
+        f"{int((mesh.cell_slots != 0).sum())} hanging-node cells")
+    res, finals = run_modes(torch, mesh, [("fp32:tiled", steps, warmup), ("fp64:tiled", steps, warmup)], stream,
+                            label="cfg4")
+    out = {"workload": f"cfg4: sphere-band octree L4/8, {mesh.n_dof} dofs, {mesh.n_cells} cells", "steps": steps,
+           "n_dof": mesh.n_dof}
+    for mode, r in res.items():
+        prod = mode.split(":")[0]
+        out[prod] = {"ms_per_step": r["ms_per_step"], "value": r["value"],
+                     "kernels_ms_avg": {c: d["ms_avg"] for c, d in r["kernels"].items()},
+                     "roofline": roofline_block(r, copy_gbs, prod)}
+    out["speedup_fp32_vs_fp64"] = res["fp32:tiled"]["value"] / res["fp64:tiled"]["value"]
+    ref = finals["fp64:tiled"]
+    out["rel_err_fp32_vs_fp64"] = float(np.abs(finals["fp32:tiled"] - ref).max() / np.abs(ref).max())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +540,8 @@ def main():
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--small", type=int, default=1000, help="steps of the small-mesh latency check (0: skip)")
     ap.add_argument("--mid", type=int, default=500, help="steps of the cache-resident 2e6-dof mesh (0: skip)")
+    ap.add_argument("--pattern-rich-steps", type=int, default=200,
+                    help="steps of the 2e7-dof all-pattern mesh, with its own roofline (0: skip)")
     ap.add_argument("--accuracy-steps", type=int, default=0,
                     help="only compare FP32 with FP64 products on the bench mesh over this many steps")
     ap.add_argument("--graph-steps", type=int, default=50, help="steps per captured graph")
@@ -537,38 +617,17 @@ def main():
         del x, y
     copy_gbs = copy_bandwidth(torch, stream)
     log(f"[bench] plain copy on this GPU: {copy_gbs:.0f} GB/s")
-    results = {}
-    finals = {}
     plan = [(m, args.steps, args.warmup) for m in args.modes.split(",") if m]
     plan += [(m, args.compare_steps, 2) for m in args.compare.split(",") if m]
-    for mode, n_steps, n_warm in plan:
-        prod, assembly = mode.split(":")
-        t1 = time.time()
-        sim = Simulation(mesh, prod=prod, assembly=assembly, stream=stream.cuda_stream)
-        log(f"[bench] {mode}: created in {time.time() - t1:.0f} s, dt={sim.dt:.4e}, "
-            f"{sim.gpu.info()['n_colours']} colours, {sim.footprint / 1e9:.1f} GB, layout {sim.gpu.layout()}")
-        ms, prof = time_mode(sim, torch, stream, n_steps, n_warm)
-        finals[mode] = sim.u()
-        results[mode] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), kernels=prof, steps=n_steps,
-                             layout=sim.gpu.layout())
-        log(f"[bench] {mode}: {ms:.3f} ms/step, {results[mode]['value']:.3e} DOF-steps/s, "
-            + ", ".join(f"{k} {v['ms_avg']:.3f} ms x{v['launches']}" for k, v in prof.items()))
-        sim.close()
-        del sim
-        torch.cuda.empty_cache()
+    results, finals = run_modes(torch, mesh, plan, stream)
 
     head = args.modes.split(",")[0]
     fp64 = next((m for m in args.modes.split(",") if m.startswith("fp64:")), None)
     r = results[head]
-    k8 = r["kernels"]["element_8node"]
-    lay = r["layout"]
-    alg8 = lay["alg_bytes_8node"]
-    if lay["alg_bytes_8node"] + lay["alg_bytes_other"] != ab["step"]:
-        log(f"[bench] warning: per-kernel algorithmic bytes {lay['alg_bytes_8node'] + lay['alg_bytes_other']} "
-            f"!= step bytes {ab['step']}")
-    achieved = alg8 / (k8["ms_avg"] * 1e-3) / 1e9 if k8["ms_avg"] > 0 else 0.0
-    kname = "tiled_step8<true, false>" if head.startswith("fp32") else "tiled_step8<false, false>"
-    traffic = counter_traffic(kname)
+    roof = roofline_block(r, copy_gbs, head.split(":")[0])
+    # the same time against the per-dof byte model (FP64 inverse mass per dof)
+    roof["alg_bytes_per_step_per_dof_model"] = ab["step"]
+    roof["step_frac_per_dof_model"] = ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -585,15 +644,7 @@ def main():
         "config": {"workload": f"{args.config}: {desc}", "n_dof": mesh.n_dof, "n_cells": mesh.n_cells,
                    "product": head.split(":")[0], "state": "fp64", "assembly": head.split(":")[1],
                    "steps_per_call": args.steps},
-        "roofline": {"bound": "hbm", "kernel": f"{kname}: owner-tile pass (regular 8-node cells, hanging-cell row forces, update)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "step_achieved": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9,
-                     "step_frac": ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                     "alg_bytes_per_launch": alg8, "alg_bytes_other_kernel": lay["alg_bytes_other"],
-                     "alg_bytes_per_step": ab["step"], "avg_launch_ms": k8["ms_avg"],
-                     "launches": k8["launches"]},
+        "roofline": roof,
         "modes": {k: dict(ms_per_step=v["ms_per_step"], value=v["value"], steps=v["steps"],
                           kernels_ms_avg={c: d["ms_avg"] for c, d in v["kernels"].items()})
                   for k, v in results.items()},
@@ -603,6 +654,8 @@ def main():
         out["speedup_vs_fp64"] = r["value"] / results[fp64]["value"]
         ref = finals[fp64]
         out["rel_err_vs_fp64"] = float(np.abs(finals[head] - ref).max() / np.abs(ref).max())
+    if args.pattern_rich_steps > 0:
+        out["pattern_rich_mesh"] = pattern_rich(torch, stream, copy_gbs, args.pattern_rich_steps, 20)
     if args.small > 0:
         out["small_mesh_step_us"] = small_mesh_latency(torch, args.small, args.graph_steps)
     if args.mid > 0:

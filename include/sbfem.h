@@ -121,7 +121,13 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
                                    void* hip_stream);
 void sbfem_destroy_patterns(sbfem_patterns* p);
 
-/* Device bytes create_mesh would allocate for this descriptor (admission control). */
+/*
+ * Device bytes create_mesh allocates for this descriptor (admission control): the sum of the
+ * sizes of the mesh's device buffers, from the same host set-up that create_mesh runs (so it
+ * costs as much host time).  A mesh of the owner-tile assembly created without u0 allocates
+ * 8 B per dof more the first time its internal force is read (read_state which = 2).
+ * Errors: those of create_mesh's validation.
+ */
 sbfem_status sbfem_mesh_footprint(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t* bytes);
 
 /* Smallest element limit 2/omega_max,e over the cells (eqs. tcr, tcr_scale). */
@@ -143,7 +149,10 @@ void sbfem_destroy_mesh(sbfem_mesh* m);
  * Advance n_steps central-difference steps (Alg. 1 time loop):
  *   R_int = sum_e s_e R_e^T K_p R_e u_e,  r = P(t_n) b - R_int,  t_n = n dt,
  *   u_{n+1} = (dt^2 M^-1 r + 2 u_n - (1 - alpha dt/2) u_{n-1}) / (1 + alpha dt/2).
- * Returns SBFEM_EUNSTABLE if the displacement became non-finite.
+ * Every step's update checks the values it writes; the first step whose u_{n+1} is not finite
+ * (time step above the stability limit) is recorded on the device.  The call is asynchronous,
+ * so that record is examined by the next call on the mesh (step_n, step_batch, read_state),
+ * which then returns SBFEM_EUNSTABLE naming the step.
  */
 sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream);
 

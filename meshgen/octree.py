@@ -90,6 +90,18 @@ class Mesh:
     def node_xyz(self):
         return self.node_lat.astype(np.float64) * (self.h0 * 2.0 ** -self.lmax)
 
+    def fingerprint(self):
+        """SHA-256 over the arrays that define the discrete problem (cells, connectivity,
+        materials, constraints, loads): stored results of a run are valid for a regenerated
+        mesh only if this matches."""
+        import hashlib
+        h = hashlib.sha256()
+        for a in (self.cell_level, self.cell_slots, self.conn_ptr, self.conn, self.cell_mat, self.mat_E,
+                  self.mat_rho, self.fixed, self.load_dof, self.load_val):
+            h.update(np.ascontiguousarray(a).tobytes())
+        h.update(repr((self.roots, self.h0, self.lmax, self.n_nodes, self.nu)).encode())
+        return h.hexdigest()
+
 
 def _upsample(a):
     return a.repeat(2, 0).repeat(2, 1).repeat(2, 2)

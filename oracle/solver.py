@@ -197,6 +197,51 @@ class Oracle:
         return out
 
 
+def sampled_step_local(mesh, u, um1, n, dt, nodes, alpha=0.0, cache=None):
+    """u_{n+1} at the given nodes from one step of eq. DnMdiag, for meshes too large for
+    :class:`Oracle`: only the cells incident to the nodes are visited.  Each node's force is
+    the sum over its cells of s_e K_e u_e (rows of the node, eq. Rinte) and its lumped mass
+    the sum of rho_e h_e^3 m_e (its entries, Sec. 3.3); fixed dofs keep a zero inverse mass;
+    the load is P(t_n) b at the node.  Same arithmetic as :meth:`Oracle.sampled_step`."""
+    cache = {} if cache is None else cache
+    nodes = np.asarray(nodes, dtype=np.int64)
+    sel = np.zeros(mesh.n_nodes, dtype=bool)
+    sel[nodes] = True
+    pos = np.flatnonzero(sel[mesh.conn])
+    cells = np.searchsorted(mesh.conn_ptr, pos, side="right") - 1
+    h = mesh.h0 * np.exp2(-mesh.cell_level[cells].astype(np.float64))
+    E = mesh.mat_E[mesh.cell_mat[cells]]
+    rho = mesh.mat_rho[mesh.cell_mat[cells]]
+    f = {int(v): np.zeros(3) for v in nodes}
+    mass = {int(v): np.zeros(3) for v in nodes}
+    for p, c, hc, Ec, rc in zip(pos, cells, h, E, rho):
+        mask = int(mesh.cell_slots[c])
+        if mask not in cache:
+            cache[mask] = Cell(mask, mesh.nu)
+        cell = cache[mask]
+        lo, hi = mesh.conn_ptr[c], mesh.conn_ptr[c + 1]
+        cn = mesh.conn[lo:hi].astype(np.int64)
+        i = int(p - lo)
+        nd = int(mesh.conn[p])
+        ue = u[(3 * cn[:, None] + np.arange(3)).ravel()]
+        f[nd] += Ec * hc * (cell.K[3 * i:3 * i + 3] @ ue)
+        mass[nd] += rc * hc ** 3 * cell.m[3 * i:3 * i + 3]
+    b = {}
+    for dof, val in zip(np.asarray(mesh.load_dof).tolist(), np.asarray(mesh.load_val).tolist()):
+        b[dof] = b.get(dof, 0.0) + val
+    P = float(loads.evaluate(mesh.load, n * dt))
+    c = 0.5 * alpha * dt
+    fixed = np.asarray(mesh.fixed).astype(bool)
+    out = np.zeros((len(nodes), 3))
+    for j, v in enumerate(nodes):
+        d = 3 * int(v) + np.arange(3)
+        minv = np.where(fixed[d], 0.0, 1.0 / mass[int(v)])
+        bv = np.array([b.get(int(x), 0.0) for x in d])
+        r = P * bv - f[int(v)]
+        out[j] = (dt * dt * minv * r + 2.0 * u[d] - (1.0 - c) * um1[d]) / (1.0 + c)
+    return out
+
+
 def relative_error(test_snaps, ref_snaps):
     """max over sampled steps of |u_test - u_ref|_inf / max over the same steps of |u_ref|_inf."""
     keys = sorted(ref_snaps)

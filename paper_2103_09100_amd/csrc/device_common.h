@@ -74,6 +74,10 @@ __device__ __forceinline__ void state_store(void* p, int32_t mode, int64_t ndof,
   q[i] = hi;
   if (mode == 2) q[ndof + i] = (float)(v - (double)hi);
 }
+// false if v, or the value the state storage keeps of it, is not finite
+__device__ __forceinline__ bool state_finite(int32_t mode, double v) {
+  return mode == 0 ? isfinite(v) : isfinite((float)v);
+}
 __device__ __forceinline__ double minv_load(const void* p, int32_t mode, int64_t i) {
   return mode == 1 ? (double)as_global((const float*)p)[i] : as_global((const double*)p)[i];
 }

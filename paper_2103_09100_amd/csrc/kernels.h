@@ -89,15 +89,19 @@ struct TiledArgs {
   const float* Ws32;    // (16-bit products: the unscaled table rounded to 16 bits, s_e in the last entry)
   const void* u;        // u_n        (state storage, see `state`)
   void* um1;            // u_{n-1} in, u_{n+1} out (owned nodes)
-  const void* minv;     // FP64, or FP32 with FP32 state
+  const void* minv;     // inverse lumped mass per node (FP64, or FP32 with FP32 state); sign bit set:
+                        // 1 + the position of the node's three values in minv_exc
+  const void* minv_exc; // three values per node whose inverse masses differ (same storage)
   double* f;            // force-only mode: R_int of owned dofs written here
+  unsigned long long* flag;    // smallest step n whose update gave a non-finite u_{n+1} (~0: none)
   const HangItem* hitems;      // hanging-cell pass
   const int32_t* hconn;
   const uint8_t* horient;
   const uint8_t* hlevel;
   const uint8_t* hmaterial;
   const HangPair* hpairs;      // per tile, its (owned dof, result) pairs
-  double* hres;                // forces of the hanging cells' rows, rewritten every step
+  void* hres;                  // forces of the hanging cells' rows, rewritten every step (FP64 for
+                               // FP64 products, else FP32)
   int64_t ndof;         // dofs of the mesh (offset of the low parts of compensated state)
   int32_t state;        // 0 FP64, 1 FP32, 2 compensated FP32 pair (hi at u[i], lo at u[ndof + i])
   int32_t round16;      // 16-bit product operands: 0 none, 1 FP16 (per-cell power-of-two scale), 2 BF16
@@ -183,6 +187,9 @@ struct TiledLaunch {
   int64_t k = 0;                       // batch: steps since the refs were recorded
   bool fp32 = false;
   bool reduced = false;                // FP32 or compensated state, or 16-bit products
+  int32_t prec = 0;                    // hanging-cell pass: sbfem_prod of the products
+  int32_t state = 0;                   // hanging-cell pass: sbfem_state of u
+  bool hang_mma = true;                // hanging-cell pass on the matrix cores (else one lane per cell)
   bool force_only = false;
   int32_t threads8 = 512, threads_mixed = 256;
   size_t lds = 0;                      // owner-tile pass
@@ -195,20 +202,32 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 void ebe_mixed_fp64_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
 void ebe_mixed_fp32_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool atomic, hipStream_t s);
 void owner_pass_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+// owner-tile pass per product precision (one translation unit each), the state storage by L.state
+void owner_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void owner_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void owner_fp16_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+void owner_bf16_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_hang_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_hang_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_hang_fp64r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
 void tiled_hang_fp32r_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s);
+// hanging-cell pass on the matrix cores, one translation unit per product precision
+void hang_mma_fp64_launch(const TiledLaunch& L, const TileWork* work, int64_t count, hipStream_t s);
+void hang_mma_fp32_launch(const TiledLaunch& L, const TileWork* work, int64_t count, hipStream_t s);
+void hang_mma_fp16_launch(const TiledLaunch& L, const TileWork* work, int64_t count, hipStream_t s);
+void hang_mma_bf16_launch(const TiledLaunch& L, const TileWork* work, int64_t count, hipStream_t s);
+// LDS bytes of a matrix-core hanging-pass block for a master of nd dofs in precision prec
+int hang_mma_lds_bytes(int prec, int nd);
 
 hipError_t launch_load(double* f, const int64_t* idx, const double* val, int64_t nnz, const LoadParams& L,
                        double t, hipStream_t s);
+// u_{n+1} = (dt2 M^-1 (-f) + 2 u_n - (1 - c) u_{n-1}) / (1 + c) over u_{n-1}, f cleared; a non-finite
+// result lowers *flag to `step` (atomic minimum)
 hipError_t launch_update(const double* un, double* unm1, double* f, const double* minv, int64_t ndof,
-                         double dt2, double c, hipStream_t s);
+                         double dt2, double c, unsigned long long* flag, int64_t step, hipStream_t s);
 hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t s);
 // refs[0..n): step += steps, parity flipped when steps is odd (graph-safe: a kernel)
 hipError_t launch_refs_advance(MeshRef* refs, int32_t n, int64_t steps, hipStream_t s);
 hipError_t launch_ref_set(MeshRef* ref, const MeshRef& v, hipStream_t s);
-hipError_t launch_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s);
-hipError_t launch_finite32(const float* a, int64_t n, int32_t* flag, hipStream_t s);
 
 }  // namespace sbfem

@@ -29,18 +29,21 @@ __global__ void load_kernel(double* __restrict__ f, const int64_t* __restrict__ 
   atomicAdd(f + idx[i], -P * val[i]);
 }
 
-// u_{n+1} written over u_{n-1}; f cleared.
+// u_{n+1} written over u_{n-1}; f cleared; the first step with a non-finite result is recorded.
 __global__ void update_kernel(const double* __restrict__ un, double* __restrict__ unm1,
                               double* __restrict__ f, const double* __restrict__ minv, int64_t ndof,
-                              double dt2, double c) {
+                              double dt2, double c, unsigned long long* __restrict__ flag, int64_t step) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const double inv = 1.0 / (1.0 + c);
+  bool bad = false;
   for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < ndof; d += stride) {
     const double r = -f[d];
     const double v = (dt2 * minv[d] * r + 2.0 * un[d] - (1.0 - c) * unm1[d]) * inv;
     unm1[d] = v;
     f[d] = 0.0;
+    bad |= !isfinite(v);
   }
+  if (bad) atomicMin(flag, (unsigned long long)step);
 }
 
 __global__ void fill_kernel(double* __restrict__ a, int64_t n, double v) {
@@ -48,15 +51,6 @@ __global__ void fill_kernel(double* __restrict__ a, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = v;
 }
 
-// flag[0] |= 1 if any entry is not finite
-template <class V>
-__global__ void finite_kernel(const V* __restrict__ a, int64_t n, int32_t* __restrict__ flag) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    bad |= !isfinite(a[i]);
-  if (bad) atomicOr(flag, 1);
-}
 
 // ---------------------------------------------------------------------------------------------
 // host-side launchers
@@ -95,8 +89,9 @@ static int grid_for(int64_t n) {
 }
 
 hipError_t launch_update(const double* un, double* unm1, double* f, const double* minv, int64_t ndof,
-                         double dt2, double c, hipStream_t s) {
-  hipLaunchKernelGGL(update_kernel, dim3(grid_for(ndof)), dim3(256), 0, s, un, unm1, f, minv, ndof, dt2, c);
+                         double dt2, double c, unsigned long long* flag, int64_t step, hipStream_t s) {
+  hipLaunchKernelGGL(update_kernel, dim3(grid_for(ndof)), dim3(256), 0, s, un, unm1, f, minv, ndof, dt2, c, flag,
+                     step);
   return hipGetLastError();
 }
 
@@ -106,19 +101,19 @@ hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finite(const double* a, int64_t n, int32_t* flag, hipStream_t s) {
-  hipLaunchKernelGGL(finite_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, a, n, flag);
-  return hipGetLastError();
-}
-
-hipError_t launch_finite32(const float* a, int64_t n, int32_t* flag, hipStream_t s) {
-  hipLaunchKernelGGL(finite_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, a, n, flag);
-  return hipGetLastError();
-}
 
 hipError_t launch_tiled(const TiledLaunch& L, hipStream_t s, const LaunchHook& hook) {
   // hanging-node cells first: they store their row forces for the owner tiles
-  if (L.n_hang > 0) {
+  if (L.n_hang > 0 && L.hang_mma) {
+    hook(2, true, s);
+    switch (L.prec) {
+      case 0: hang_mma_fp64_launch(L, L.work_hang, L.n_hang, s); break;
+      case 1: hang_mma_fp32_launch(L, L.work_hang, L.n_hang, s); break;
+      case 2: hang_mma_fp16_launch(L, L.work_hang, L.n_hang, s); break;
+      default: hang_mma_bf16_launch(L, L.work_hang, L.n_hang, s); break;
+    }
+    hook(2, false, s);
+  } else if (L.n_hang > 0) {
     hook(2, true, s);
     if (L.fp32)
       (L.reduced ? tiled_hang_fp32r_launch : tiled_hang_fp32_launch)(L, L.work_hang, 0, L.n_hang, s);
@@ -172,20 +167,12 @@ void ebe8_launch(const ElementArgs& a, const Tile* tiles, int64_t n, bool fp32, 
 }
 
 // owner-tile pass: one block per tile (per (mesh, tile) in a batch)
-template <bool F, bool R>
-static void owner_pass(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
-  if (L.lds > 65536)
-    (void)hipFuncSetAttribute((const void*)tiled_step8<F, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds);
-  const int64_t blocks = 8 * ((count + 7) / 8);
-  hipLaunchKernelGGL((tiled_step8<F, R>), dim3((unsigned)blocks), dim3(L.threads8), L.lds, s, L.single, L.refs, work,
-                     first, count, L.k, (int)L.force_only);
-}
-
 void owner_pass_launch(const TiledLaunch& L, const TileWork* work, int64_t first, int64_t count, hipStream_t s) {
-  if (L.fp32) {
-    if (L.reduced) owner_pass<true, true>(L, work, first, count, s); else owner_pass<true, false>(L, work, first, count, s);
-  } else {
-    if (L.reduced) owner_pass<false, true>(L, work, first, count, s); else owner_pass<false, false>(L, work, first, count, s);
+  switch (L.prec) {
+    case 0: owner_fp64_launch(L, work, first, count, s); break;
+    case 1: owner_fp32_launch(L, work, first, count, s); break;
+    case 2: owner_fp16_launch(L, work, first, count, s); break;
+    default: owner_bf16_launch(L, work, first, count, s); break;
   }
 }
 

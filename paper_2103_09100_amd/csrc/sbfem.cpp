@@ -192,7 +192,8 @@ struct sbfem_mesh {
   void* u = nullptr;     // state storage per state_mode: FP64, FP32 or compensated FP32 pair
   void* um1 = nullptr;
   double* f = nullptr;
-  void* minv = nullptr;  // FP64, or FP32 with FP32 state
+  void* minv = nullptr;  // per dof (classic assemblies, FP64); per node (owner tiles, see TiledArgs)
+  void* minv_exc = nullptr;  // owner tiles: three values per node whose inverse masses differ
   double* matE = nullptr;
   int32_t* conn = nullptr;
   uint8_t* orient = nullptr;
@@ -202,8 +203,8 @@ struct sbfem_mesh {
   int64_t* load_idx = nullptr;
   double* load_val = nullptr;
   int64_t nnz = 0;
-  int32_t* flag_d = nullptr;
-  int32_t* flag_h = nullptr;
+  unsigned long long* flag_d = nullptr;  // first step with a non-finite update (~0: none), device
+  unsigned long long* flag_h = nullptr;  // its copy in pinned host memory
   hipEvent_t flag_ev = nullptr;
   bool flag_pending = false;
   std::vector<sbfem::TileRange> groups;  // one per colour
@@ -233,7 +234,8 @@ struct sbfem_mesh {
   uint8_t* hlevel = nullptr;
   uint8_t* hmaterial = nullptr;
   sbfem::HangPair* hpairs = nullptr;    // per owner tile: (owned dof, result index) of hanging rows
-  double* hres = nullptr;               // row forces of the hanging cells (hanging-cell pass output)
+  void* hres = nullptr;                 // row forces of the hanging cells (hanging-cell pass output)
+  bool hang_mma = true;                 // hanging-cell pass on the matrix cores
   int64_t n_hang = 0;
   int64_t lds_hang = 0;                 // LDS of a hanging-pass block (its pattern's matrix)
   int32_t tile_nodes = 0;
@@ -291,14 +293,474 @@ sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
   return SBFEM_OK;
 }
 
-int64_t footprint_bytes(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t total_conn) {
-  const int64_t ndof = 3 * d->n_nodes;
-  int64_t b = 2 * state_bytes(d->state, ndof) + ndof * 8;  // u, u_prev, f
-  b += ndof * (d->state == SBFEM_STATE_FP32 ? 4 : 8);       // minv
-  b += total_conn * 4 + d->n_cells * 3;         // node ids, orientation, level, material
-  b += ((d->n_cells + sbfem::kTile - 1) / sbfem::kTile + p->n * 64) * (int64_t)sizeof(sbfem::Tile);
-  b += d->load_nnz * 16 + 256 * 8 + 64;
+// Host plan of a mesh (Alg. 1 set-up): internal numbering, normalised orientations, lumped
+// mass, load vector, and the layout of the chosen assembly, with every device buffer's size.
+// create_mesh uploads a plan; mesh_footprint returns the bytes of the same buffers.
+struct MeshPlan {
+  int64_t N = 0, C = 0, ndof = 0;
+  std::vector<int64_t> cptr;          // offsets into conn per cell (input order)
+  std::vector<int32_t> int2ext;       // internal node -> caller node
+  std::vector<int32_t> iconn;         // internal node ids per cell (master order)
+  std::vector<uint8_t> orient;        // orientation per cell (8-node cells re-listed in identity)
+  std::vector<double> mdiag, minv;    // lumped mass and its inverse (0 on fixed dofs), internal dofs
+  std::vector<int64_t> bidx;          // load vector, internal dofs, duplicates merged
+  std::vector<double> bval;
+  std::vector<double> matE;           // 256 entries
+  bool force_array = false;           // an FP64 force array over all dofs is allocated
+  // owner tiles: inverse mass per node (bits of the FP64 value, or FP32 with FP32 state); a node
+  // whose three values differ has the sign bit set and 1 + its position in the exception table
+  std::vector<uint64_t> mnode64;
+  std::vector<uint32_t> mnode32;
+  std::vector<double> mexc64;
+  std::vector<float> mexc32;
+  int64_t n_exc = 0;
+  // owner tiles
+  sbfem::TilingOutput to;
+  int32_t lds_bytes = 0, block_threads = 512, block_threads_mixed = 256;
+  bool walsh = true;
+  bool hang_mma = true;               // hanging-cell pass on the matrix cores
+  std::vector<sbfem::HangItem> hitems;
+  std::vector<int32_t> hconn;
+  std::vector<uint8_t> hor, hlev, hmat;
+  std::vector<sbfem::HangPair> hpairs;
+  int64_t n_res = 0, lds_hang = 0;
+  std::vector<double> ws64;
+  std::vector<float> ws32;
+  int64_t layout[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // classic assemblies
+  std::vector<int32_t> sconn;
+  std::vector<uint8_t> sorient, slevel, smat;
+  std::vector<sbfem::Tile> tiles;
+  std::vector<sbfem::TileRange> groups;
+  int n_colours = 1;
+};
+
+// Every device buffer of a mesh with its size in bytes, in allocation order: f(slot, bytes),
+// where slot is the mesh member that holds it (null when m is null, for the footprint).
+template <class F>
+void for_each_buffer(const MeshPlan& P, const sbfem_mesh_desc* d, sbfem_mesh* m, F f) {
+  auto slot = [&](auto member) -> void** { return m ? (void**)&(m->*member) : nullptr; };
+  const int64_t ndof = P.ndof;
+  f(slot(&sbfem_mesh::u), (size_t)state_bytes(d->state, ndof));
+  f(slot(&sbfem_mesh::um1), (size_t)state_bytes(d->state, ndof));
+  const size_t mval = d->state == SBFEM_STATE_FP32 ? 4 : 8;
+  if (d->assembly == SBFEM_ASM_TILED) {
+    f(slot(&sbfem_mesh::minv), (size_t)P.N * mval);
+    f(slot(&sbfem_mesh::minv_exc), (size_t)(3 * P.n_exc) * mval);
+  } else {
+    f(slot(&sbfem_mesh::minv), (size_t)ndof * 8);
+  }
+  if (P.force_array) f(slot(&sbfem_mesh::f), (size_t)(ndof * 8));
+  f(slot(&sbfem_mesh::matE), 256 * 8);
+  f(slot(&sbfem_mesh::flag_d), sizeof(unsigned long long));
+  if (d->assembly == SBFEM_ASM_TILED) {
+    const auto& to = P.to;
+    f(slot(&sbfem_mesh::otiles), to.tiles.size() * sizeof(sbfem::OwnerTile));
+    f(slot(&sbfem_mesh::items), to.items.size() * sizeof(sbfem::CellItem));
+    f(slot(&sbfem_mesh::lidx), to.lidx.size() * 2);
+    f(slot(&sbfem_mesh::nodelist), to.nodelist.size() * 4);
+    f(slot(&sbfem_mesh::tloads), to.loads.size() * sizeof(sbfem::LoadEntry));
+    f(slot(&sbfem_mesh::hitems), P.hitems.size() * sizeof(sbfem::HangItem));
+    f(slot(&sbfem_mesh::hconn), P.hconn.size() * 4);
+    f(slot(&sbfem_mesh::horient), P.hor.size());
+    f(slot(&sbfem_mesh::hlevel), P.hlev.size());
+    f(slot(&sbfem_mesh::hmaterial), P.hmat.size());
+    f(slot(&sbfem_mesh::hpairs), std::max<size_t>(1, P.hpairs.size()) * sizeof(sbfem::HangPair));
+    f(slot(&sbfem_mesh::hres), (size_t)std::max<int64_t>(1, P.n_res) * (d->prod == SBFEM_PROD_FP64 ? 8 : 4));
+    f(slot(&sbfem_mesh::d_args), 2 * sizeof(sbfem::TiledArgs));
+    f(slot(&sbfem_mesh::d_ref), sizeof(sbfem::MeshRef));
+    f(slot(&sbfem_mesh::dWs64), P.ws64.size() * 8);
+    f(slot(&sbfem_mesh::dWs32), P.ws32.size() * 4);
+  } else {
+    f(slot(&sbfem_mesh::conn), P.iconn.size() * 4);
+    f(slot(&sbfem_mesh::orient), (size_t)P.C);
+    f(slot(&sbfem_mesh::level), (size_t)P.C);
+    f(slot(&sbfem_mesh::material), (size_t)P.C);
+    f(slot(&sbfem_mesh::tiles), P.tiles.size() * sizeof(sbfem::Tile));
+    f(slot(&sbfem_mesh::load_idx), P.bidx.size() * 8);
+    f(slot(&sbfem_mesh::load_val), P.bval.size() * 8);
+  }
+}
+
+int64_t plan_bytes(const MeshPlan& P, const sbfem_mesh_desc* d) {
+  int64_t b = 0;
+  for_each_buffer(P, d, nullptr, [&](void**, size_t bytes) { b += (int64_t)bytes; });
   return b;
+}
+
+sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPlan& P) {
+  sbfem_status st = validate_desc(p, d);
+  if (st != SBFEM_OK) return st;
+  const int64_t N = d->n_nodes, C = d->n_cells, ndof = 3 * N;
+  P.N = N;
+  P.C = C;
+  P.ndof = ndof;
+  // per-cell node counts and offsets into conn (input order)
+  P.cptr.assign(C + 1, 0);
+  for (int64_t c = 0; c < C; ++c) P.cptr[c + 1] = P.cptr[c] + p->ndof[d->pattern[c]] / 3;
+  const std::vector<int64_t>& cptr = P.cptr;
+  const int64_t total = cptr[C];
+  for (int64_t i = 0; i < total; ++i)
+    if (d->conn[i] < 0 || d->conn[i] >= N)
+      return fail(SBFEM_EINVAL, "node id %d at conn[%lld] out of range", d->conn[i], (long long)i);
+
+  // internal numbering: first touch along the cell order (nodes used by no cell go last)
+  std::vector<int32_t> ext2int(N, -1);
+  P.int2ext.resize(N);
+  {
+    int32_t next = 0;
+    for (int64_t i = 0; i < total; ++i) {
+      const int32_t g = d->conn[i];
+      if (ext2int[g] < 0) {
+        ext2int[g] = next;
+        P.int2ext[next++] = g;
+      }
+    }
+    for (int64_t g = 0; g < N; ++g)
+      if (ext2int[g] < 0) {
+        ext2int[g] = next;
+        P.int2ext[next++] = (int32_t)g;
+      }
+  }
+  P.iconn.resize(total);
+  std::vector<int32_t>& iconn = P.iconn;
+  for (int64_t i = 0; i < total; ++i) iconn[i] = ext2int[d->conn[i]];
+  // Cells of the 8-node pattern, whose matrix (and lumped mass) is invariant under the
+  // 48 cube transformations, are re-listed in identity orientation: the master matrix
+  // applies to the cell's own corner order and no transformation is needed per step.
+  P.orient.assign(d->orient, d->orient + C);
+  std::vector<uint8_t>& orient = P.orient;
+  if (p->p8 >= 0) {
+    for (int64_t c = 0; c < C; ++c) {
+      if (d->pattern[c] != p->p8 || orient[c] == 0) continue;
+      int pi[3], nat[8];
+      double sg[3];
+      decode(orient[c], pi, sg);
+      for (int k = 0; k < 8; ++k) nat[corner_image(k, pi, sg)] = iconn[cptr[c] + k];
+      for (int k = 0; k < 8; ++k) iconn[cptr[c] + k] = nat[k];
+      orient[c] = 0;
+    }
+  }
+
+  // lumped diagonal mass in internal numbering (summation order fixed: cell order)
+  P.mdiag.assign(ndof, 0.0);
+  for (int64_t c = 0; c < C; ++c) {
+    const int pid = d->pattern[c];
+    const double h = std::ldexp(d->h0, -(int)d->level[c]);
+    const double sc = d->rho[d->material[c]] * h * h * h;
+    int pi[3];
+    double sg[3];
+    decode(orient[c], pi, sg);
+    const double* mp = p->m.data() + p->moff[pid];
+    for (int64_t k = 0; k < cptr[c + 1] - cptr[c]; ++k)
+      for (int a = 0; a < 3; ++a) P.mdiag[3 * (int64_t)iconn[cptr[c] + k] + pi[a]] += sc * mp[3 * k + a];
+  }
+  P.minv.resize(ndof);
+  for (int64_t i = 0; i < ndof; ++i) {
+    const int64_t e = 3 * (int64_t)P.int2ext[i / 3] + i % 3;
+    if (d->fixed_dof && d->fixed_dof[e]) {
+      P.minv[i] = 0.0;
+    } else {
+      if (!(P.mdiag[i] > 0))
+        return fail(SBFEM_EINVAL, "free dof %lld has no mass (node not used by any cell?)", (long long)e);
+      P.minv[i] = 1.0 / P.mdiag[i];
+    }
+  }
+
+  // load vector (internal dofs) with merged duplicates
+  std::map<int64_t, double> bmap;
+  for (int64_t i = 0; i < d->load_nnz; ++i) {
+    if (d->load_dof[i] < 0 || d->load_dof[i] >= ndof)
+      return fail(SBFEM_EINVAL, "load dof %lld out of range", (long long)d->load_dof[i]);
+    const int64_t e = d->load_dof[i];
+    bmap[3 * (int64_t)ext2int[e / 3] + e % 3] += d->load_val[i];
+  }
+  for (auto& kv : bmap) {
+    P.bidx.push_back(kv.first);
+    P.bval.push_back(kv.second);
+  }
+  std::vector<int32_t>().swap(ext2int);
+  P.matE.assign(256, 0.0);
+  for (int i = 0; i < d->n_materials; ++i) P.matE[i] = d->E[i];
+  // the owner-tile step keeps no force array; the start-up with u0 needs one (K u0)
+  P.force_array = d->assembly != SBFEM_ASM_TILED || d->u0 != nullptr;
+  if (d->assembly == SBFEM_ASM_TILED) {
+    // inverse mass per node; a node whose three stored values differ goes to the exception table
+    const bool f32 = d->state == SBFEM_STATE_FP32;
+    if (f32)
+      P.mnode32.resize(N);
+    else
+      P.mnode64.resize(N);
+    for (int64_t n = 0; n < N; ++n) {
+      const double* mi = P.minv.data() + 3 * n;
+      if (f32) {
+        const float v0 = (float)mi[0], v1 = (float)mi[1], v2 = (float)mi[2];
+        if (v0 == v1 && v1 == v2) {
+          std::memcpy(&P.mnode32[n], &v0, 4);
+        } else {
+          if (P.n_exc + 1 >= (int64_t)0x7FFFFFFF) return fail(SBFEM_EINVAL, "too many nodes with direction-dependent masses");
+          P.mexc32.insert(P.mexc32.end(), {v0, v1, v2});
+          P.mnode32[n] = 0x80000000u | (uint32_t)(++P.n_exc);
+        }
+      } else {
+        if (mi[0] == mi[1] && mi[1] == mi[2]) {
+          std::memcpy(&P.mnode64[n], &mi[0], 8);
+        } else {
+          P.mexc64.insert(P.mexc64.end(), {mi[0], mi[1], mi[2]});
+          P.mnode64[n] = 0x8000000000000000ull | (uint64_t)(++P.n_exc);
+        }
+      }
+    }
+  }
+
+  if (d->assembly == SBFEM_ASM_TILED) {
+    sbfem::TilingInput ti;
+    ti.n_nodes = N;
+    ti.n_cells = C;
+    ti.cptr = cptr.data();
+    ti.conn = iconn.data();
+    ti.pattern = d->pattern;
+    ti.orient = orient.data();
+    ti.level = d->level;
+    ti.material = d->material;
+    ti.pattern_ndof = p->ndof.data();
+    ti.pattern_koff = p->koff.data();
+    ti.load_dof = P.bidx;
+    ti.load_val = P.bval;
+    sbfem::TilingOutput& to = P.to;
+    // tile size: env SBFEM_TILE_NODES or the default; halved until one block's LDS
+    // (u of its local nodes + f of its owned ones) fits the per-block limit
+    int device = 0, lds_max = 65536;
+    (void)hipGetDevice(&device);
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (lds_max < 16384) lds_max = 65536;
+    int32_t tn0 = kOwnerTileNodes;
+    if (const char* ev = std::getenv("SBFEM_TILE_NODES")) tn0 = std::max(32, std::atoi(ev));
+    auto threads_env = [](const char* name, int32_t& v) {
+      if (const char* ev = std::getenv(name)) {
+        const int bt = std::atoi(ev);
+        if (bt >= 64 && bt <= 512 && bt % 64 == 0) v = bt;
+      }
+    };
+    threads_env("SBFEM_BLOCK_THREADS", P.block_threads);
+    threads_env("SBFEM_BLOCK_THREADS_MIXED", P.block_threads_mixed);
+    // explicit descriptor values win over the defaults and the environment
+    auto threads_desc = [](int32_t v, int32_t& out) {
+      if (v >= 64 && v <= 512 && v % 64 == 0) out = v;
+    };
+    threads_desc(d->block_threads, P.block_threads);
+    threads_desc(d->block_threads_mixed, P.block_threads_mixed);
+    if (d->tile_nodes > 0) tn0 = std::max(32, d->tile_nodes);
+    if (const char* ev = std::getenv("SBFEM_DENSE8")) P.walsh = std::atoi(ev) == 0;
+    ti.p8 = P.walsh ? p->p8 : -1;
+    bool ok = false;
+    // LDS per block: FP64 forces of the owned nodes, u of the local nodes (FP64: 24 B per node;
+    // FP32: 16-byte float4 nodes)
+    const int64_t node_bytes = d->prod != SBFEM_PROD_FP64 ? 16 : 24;
+    for (int32_t tn = tn0; tn >= 32; tn /= 2) {
+      if (!sbfem::build_owner_tiles(ti, tn, to)) continue;
+      // forces of the owned nodes rounded up to an even number of doubles (16-byte aligned u)
+      const int64_t fbytes = 8 * ((3 * (int64_t)to.tile_nodes + 1) & ~(int64_t)1);
+      if (node_bytes * to.max_local + fbytes <= lds_max) {
+        P.lds_bytes = (int32_t)(node_bytes * to.max_local + fbytes);
+        ok = true;
+        break;
+      }
+    }
+    if (!ok) return fail(SBFEM_EINVAL, "no owner-tile size fits the on-chip memory of a block");
+    // hanging-node cells (every cell that is not a regular 8-node cell), each once: items of up
+    // to a wave of cells of one pattern, in cell order within a pattern; node ids slot-major
+    std::vector<int64_t> hcells;
+    for (int64_t c = 0; c < C; ++c)
+      if (ti.p8 < 0 || d->pattern[c] != ti.p8) hcells.push_back(c);
+    std::stable_sort(hcells.begin(), hcells.end(),
+                     [&](int64_t x, int64_t y) { return d->pattern[x] < d->pattern[y]; });
+    // the items of one hanging-pass block share a pattern: each pattern's items are padded with
+    // empty items to whole blocks; the block stages that pattern's matrix in LDS
+    const int per_block = P.block_threads_mixed / sbfem::kWave;
+    std::vector<std::pair<int64_t, sbfem::HangPair>> tpairs;  // (tile, pair)
+    int64_t kl_max = 0;  // entries of the largest staged matrix (rows padded to 4)
+    for (size_t i0 = 0; i0 < hcells.size();) {
+      const int pid = d->pattern[hcells[i0]];
+      size_t i1 = i0;
+      while (i1 < hcells.size() && i1 - i0 < (size_t)sbfem::kWave && d->pattern[hcells[i1]] == pid) ++i1;
+      sbfem::HangItem it{};
+      it.res0 = P.n_res;
+      it.cell0 = (int64_t)P.hor.size();
+      it.conn0 = (int64_t)P.hconn.size();
+      it.koff = p->koff[pid];
+      it.nn = p->ndof[pid] / 3;
+      it.count = (int32_t)(i1 - i0);
+      for (int k = 0; k < it.nn; ++k)
+        for (size_t j = i0; j < i1; ++j) P.hconn.push_back(iconn[cptr[hcells[j]] + k]);
+      for (size_t j = i0; j < i1; ++j) {
+        P.hor.push_back(orient[hcells[j]]);
+        P.hlev.push_back(d->level[hcells[j]]);
+        P.hmat.push_back(d->material[hcells[j]]);
+      }
+      P.hitems.push_back(it);
+      const int64_t nd = p->ndof[pid];
+      // row r of lane j: dof 3 g_k + pi(a) (r = 3k + a) of the tile that owns node g_k
+      for (size_t j = i0; j < i1; ++j) {
+        const int64_t c = hcells[j];
+        int pi[3];
+        double sg[3];
+        decode(orient[c], pi, sg);
+        for (int r = 0; r < nd; ++r) {
+          const int64_t g = iconn[cptr[c] + r / 3];
+          const int64_t t = g / to.tile_nodes;
+          const int64_t ri = P.n_res + (int64_t)r * sbfem::kWave + (int64_t)(j - i0);
+          tpairs.push_back({t, {(int32_t)(3 * (g - t * to.tile_nodes) + pi[r % 3]), (uint32_t)ri}});
+        }
+      }
+      P.n_res += nd * sbfem::kWave;
+      kl_max = std::max<int64_t>(kl_max, nd * ((nd + 3) & ~3));
+      i0 = i1;
+      if (i0 == hcells.size() || d->pattern[hcells[i0]] != pid) {
+        sbfem::HangItem pad = it;
+        pad.count = 0;
+        while (P.hitems.size() % per_block) P.hitems.push_back(pad);
+      }
+    }
+    if (const char* ev = std::getenv("SBFEM_HANG")) P.hang_mma = std::strcmp(ev, "valu") != 0;
+    if (P.hang_mma) {
+      P.lds_hang = 0;
+      for (const auto& it : P.hitems) P.lds_hang = std::max<int64_t>(P.lds_hang, sbfem::hang_mma_lds_bytes(d->prod, 3 * it.nn));
+    } else {
+      P.lds_hang = kl_max * (d->prod == SBFEM_PROD_FP64 ? 8 : 4);
+    }
+    if (P.n_res > (int64_t)UINT32_MAX) return fail(SBFEM_EINVAL, "too many hanging-node cells for 32-bit result indices");
+    // pairs grouped by owner tile (each tile's pairs in result order)
+    std::stable_sort(tpairs.begin(), tpairs.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    P.hpairs.resize(tpairs.size());
+    for (size_t i = 0; i < tpairs.size(); ++i) {
+      P.hpairs[i] = tpairs[i].second;
+      auto& ot = to.tiles[tpairs[i].first];
+      if (ot.n_hpair == 0) ot.hpair0 = (int64_t)i;
+      ot.n_hpair++;
+    }
+    std::vector<std::pair<int64_t, sbfem::HangPair>>().swap(tpairs);
+    P.layout[0] = to.n_pure8;
+    P.layout[1] = to.n_mixed;
+    P.layout[2] = (int64_t)to.items.size();
+    P.layout[3] = to.local_entries;
+    P.layout[4] = (int64_t)hcells.size();  // regular cell entries over all tiles, plus the hanging cells
+    for (const auto& it : to.items) P.layout[4] += it.count;
+    P.layout[5] = to.tile_nodes;
+    // algorithmic bytes per step of each pass (the method's own traffic, whatever the layout):
+    // the owner-tile pass reads u_n, u_{n-1} and writes u_{n+1} of every dof (in the state
+    // storage: 8 B per value for FP64 and the compensated pair, 4 B for FP32), reads the
+    // inverse mass (one value per node, three for a node whose values differ; 8 B, 4 B with
+    // FP32 state), the node ids (4 B each) and orientation, level, material (1 B each) of the
+    // regular 8-node cells, and the load entries (16 B); the hanging-cell pass the same
+    // per-cell bytes of the other cells
+    {
+      const int64_t bs = d->state == SBFEM_STATE_FP32 ? 4 : 8;
+      int64_t b8 = 3 * bs * ndof + bs * (N + 3 * P.n_exc) + 16 * (int64_t)P.bidx.size(), bo = 0;
+      for (int64_t c = 0; c < C; ++c) (ti.p8 >= 0 && d->pattern[c] == ti.p8 ? b8 : bo) += 4 * (cptr[c + 1] - cptr[c]) + 3;
+      P.layout[6] = b8;
+      P.layout[7] = bo;
+    }
+    P.layout[8] = to.max_local;
+    P.layout[9] = P.lds_bytes;
+    // structured Walsh table pre-multiplied by s_e = E h of each scale class (one rounding per entry)
+    const size_t ncls = to.scale_keys.size();
+    const int WC = sbfem::kWalshC;
+    P.ws64.assign(std::max<size_t>(1, ncls) * WC, 0.0);
+    P.ws32.assign(P.ws64.size(), 0.0f);
+    for (size_t c = 0; c < ncls; ++c) {
+      const int lev = to.scale_keys[c] >> 8, mat = to.scale_keys[c] & 255;
+      const double se = d->E[mat] * std::ldexp(d->h0, -lev);
+      for (int i = 0; i < WC; ++i) {
+        P.ws64[WC * c + i] = se * p->Wc[i];
+        P.ws32[WC * c + i] = (float)P.ws64[WC * c + i];
+      }
+      if (d->prod == SBFEM_PROD_FP16 || d->prod == SBFEM_PROD_BF16) {
+        // 16-bit operands: the unscaled coefficients rounded to 16 bits, s_e applied after
+        for (int i = 0; i < WC - 1; ++i)
+          P.ws32[WC * c + i] = d->prod == SBFEM_PROD_FP16 ? round_fp16((float)p->Wc[i]) : round_bf16((float)p->Wc[i]);
+        P.ws32[WC * c + WC - 1] = (float)se;
+      }
+    }
+    return SBFEM_OK;
+  }
+
+  // classic assemblies: colours greedy in input order, per-node mask of the colours already
+  // touching it
+  std::vector<uint8_t> colour(C, 0);
+  int n_colours = 1;
+  if (d->assembly == SBFEM_ASM_COLOUR) {
+    std::vector<uint64_t> used(N, 0);
+    for (int64_t c = 0; c < C; ++c) {
+      uint64_t forb = 0;
+      for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) forb |= used[iconn[i]];
+      if (forb == ~0ull) return fail(SBFEM_EINVAL, "cell %lld needs more than 64 colours", (long long)c);
+      int col = 0;
+      while ((forb >> col) & 1) ++col;
+      colour[c] = (uint8_t)col;
+      n_colours = std::max(n_colours, col + 1);
+      for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) used[iconn[i]] |= 1ull << col;
+    }
+  }
+  P.n_colours = n_colours;
+  // order: colour, 8-node class first, pattern; stable in input order (counting sort)
+  const int64_t n_keys = (int64_t)n_colours * 2 * p->n;
+  auto key = [&](int64_t c) -> int64_t {
+    const int pid = d->pattern[c];
+    const int mixed = p->ndof[pid] == 24 ? 0 : 1;
+    return ((int64_t)colour[c] * 2 + mixed) * p->n + pid;
+  };
+  std::vector<int64_t> order(C);
+  {
+    std::vector<int64_t> start(n_keys + 1, 0);
+    for (int64_t c = 0; c < C; ++c) start[key(c) + 1]++;
+    for (int64_t k = 0; k < n_keys; ++k) start[k + 1] += start[k];
+    for (int64_t c = 0; c < C; ++c) order[start[key(c)]++] = c;
+  }
+  // segments, tiles and slot-major node ids
+  P.sconn.resize(total);
+  P.sorient.resize(C);
+  P.slevel.resize(C);
+  P.smat.resize(C);
+  P.groups.assign(n_colours, sbfem::TileRange{-1, 0, 0});
+  int64_t cpos = 0, i0 = 0;
+  while (i0 < C) {
+    int64_t i1 = i0;
+    const int64_t k0 = key(order[i0]);
+    while (i1 < C && key(order[i1]) == k0) ++i1;
+    const int pid = d->pattern[order[i0]];
+    const int nn = p->ndof[pid] / 3;
+    const int col = colour[order[i0]];
+    const int64_t cnt = i1 - i0;
+    for (int64_t j = 0; j < cnt; ++j) {
+      const int64_t c = order[i0 + j];
+      for (int k = 0; k < nn; ++k) P.sconn[cpos + (int64_t)k * cnt + j] = iconn[cptr[c] + k];
+      P.sorient[i0 + j] = orient[c];
+      P.slevel[i0 + j] = d->level[c];
+      P.smat[i0 + j] = d->material[c];
+    }
+    auto& g = P.groups[col];
+    if (g.first < 0) g.first = (int64_t)P.tiles.size();
+    for (int64_t j = 0; j < cnt; j += sbfem::kTile) {
+      sbfem::Tile t;
+      t.cell0 = i0 + j;
+      t.conn0 = cpos + j;
+      t.stride = cnt;
+      t.koff = p->koff[pid];
+      t.count = (int32_t)std::min<int64_t>(sbfem::kTile, cnt - j);
+      t.nn = nn;
+      P.tiles.push_back(t);
+      if (nn == 8)
+        g.n_fixed8++;
+      else
+        g.n_mixed++;
+    }
+    cpos += cnt * nn;
+    i0 = i1;
+  }
+  for (auto& g : P.groups)
+    if (g.first < 0) g.first = 0;
+  return SBFEM_OK;
 }
 
 }  // namespace
@@ -473,20 +935,25 @@ void sbfem_destroy_patterns(sbfem_patterns* p) {
 
 sbfem_status sbfem_mesh_footprint(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t* bytes) {
   if (!p || !d || !bytes) return fail(SBFEM_EINVAL, "null argument");
-  int64_t tc = 0;
-  for (int64_t c = 0; c < d->n_cells; ++c) {
-    if (d->pattern[c] >= p->n) return fail(SBFEM_EINVAL, "pattern out of range");
-    tc += p->ndof[d->pattern[c]] / 3;
-  }
-  *bytes = footprint_bytes(p, d, tc);
+  MeshPlan P;
+  sbfem_status st = plan_mesh(p, d, P);
+  if (st != SBFEM_OK) return st;
+  *bytes = plan_bytes(P, d);
   return SBFEM_OK;
 }
 
 sbfem_status sbfem_critical_dt(const sbfem_patterns* p, const sbfem_mesh_desc* d, double* dt_cr) {
   if (!dt_cr) return fail(SBFEM_EINVAL, "null output");
-  sbfem_status st = validate_desc(p, d);
-  if (st != SBFEM_OK && st != SBFEM_EINVAL) return st;
-  if (!p || !d || d->n_cells <= 0) return fail(SBFEM_EINVAL, "empty mesh");
+  // only what the limit needs: the cell arrays it reads and the material table (the time step
+  // itself need not be set yet)
+  if (!p || !d) return fail(SBFEM_EINVAL, "null patterns or descriptor");
+  if (d->n_cells <= 0) return fail(SBFEM_EINVAL, "empty mesh");
+  if (!d->pattern || !d->level || !d->material) return fail(SBFEM_EINVAL, "missing cell arrays");
+  if (d->n_materials <= 0 || d->n_materials > 256 || !d->E || !d->rho)
+    return fail(SBFEM_EINVAL, "bad material table");
+  for (int i = 0; i < d->n_materials; ++i)
+    if (!(d->E[i] > 0) || !(d->rho[i] > 0)) return fail(SBFEM_EINVAL, "material %d: E and rho must be > 0", i);
+  if (!(d->h0 > 0)) return fail(SBFEM_EINVAL, "h0 must be > 0");
   double best = INFINITY;
   for (int64_t c = 0; c < d->n_cells; ++c) {
     const int pid = d->pattern[c];
@@ -554,6 +1021,7 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->alloc, m->um1);
   dfree(m->alloc, m->f);
   dfree(m->alloc, m->minv);
+  dfree(m->alloc, m->minv_exc);
   dfree(m->alloc, m->matE);
   dfree(m->alloc, m->conn);
   dfree(m->alloc, m->orient);
@@ -644,7 +1112,9 @@ static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const void* u, void*
   a.u = u;
   a.um1 = um1;
   a.minv = m->minv;
+  a.minv_exc = m->minv_exc;
   a.f = m->f;
+  a.flag = m->flag_d;
   a.ndof = m->ndof;
   a.state = m->state_mode;
   a.round16 = m->prod == SBFEM_PROD_FP16 ? 1 : (m->prod == SBFEM_PROD_BF16 ? 2 : 0);
@@ -671,6 +1141,9 @@ static sbfem::TiledLaunch tiled_launch(const sbfem_mesh* m, bool force_only) {
   L.fp32 = m->prod != SBFEM_PROD_FP64;  // FP32 kernels also carry the 16-bit product forms
   L.reduced = m->state_mode != SBFEM_STATE_FP64 || m->prod == SBFEM_PROD_FP16 || m->prod == SBFEM_PROD_BF16;
   L.force_only = force_only;
+  L.prec = m->prod;
+  L.state = m->state_mode;
+  L.hang_mma = m->hang_mma;
   L.threads8 = m->block_threads;
   L.threads_mixed = m->block_threads_mixed;
   L.lds = (size_t)m->lds_bytes;
@@ -693,60 +1166,18 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
                                void* hip_stream) {
   if (!out) return fail(SBFEM_EINVAL, "null output handle");
   *out = nullptr;
-  sbfem_status st = validate_desc(p, d);
+  MeshPlan P;
+  sbfem_status st = plan_mesh(p, d, P);
   if (st != SBFEM_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
-  const int64_t N = d->n_nodes, C = d->n_cells, ndof = 3 * N;
-
-  // per-cell node counts and offsets into conn (input order)
-  std::vector<int64_t> cptr(C + 1, 0);
-  for (int64_t c = 0; c < C; ++c) cptr[c + 1] = cptr[c] + p->ndof[d->pattern[c]] / 3;
-  const int64_t total = cptr[C];
-  for (int64_t i = 0; i < total; ++i)
-    if (d->conn[i] < 0 || d->conn[i] >= N)
-      return fail(SBFEM_EINVAL, "node id %d at conn[%lld] out of range", d->conn[i], (long long)i);
-
-  // internal numbering: first touch along the cell order (nodes used by no cell go last)
-  std::vector<int32_t> ext2int(N, -1), int2ext(N);
-  {
-    int32_t next = 0;
-    for (int64_t i = 0; i < total; ++i) {
-      const int32_t g = d->conn[i];
-      if (ext2int[g] < 0) {
-        ext2int[g] = next;
-        int2ext[next++] = g;
-      }
-    }
-    for (int64_t g = 0; g < N; ++g)
-      if (ext2int[g] < 0) {
-        ext2int[g] = next;
-        int2ext[next++] = (int32_t)g;
-      }
-  }
-  std::vector<int32_t> iconn(total);
-  for (int64_t i = 0; i < total; ++i) iconn[i] = ext2int[d->conn[i]];
-  // Cells of the 8-node pattern, whose matrix (and lumped mass) is invariant under the
-  // 48 cube transformations, are re-listed in identity orientation: the master matrix
-  // applies to the cell's own corner order and no transformation is needed per step.
-  std::vector<uint8_t> orient(d->orient, d->orient + C);
-  if (p->p8 >= 0) {
-    for (int64_t c = 0; c < C; ++c) {
-      if (d->pattern[c] != p->p8 || orient[c] == 0) continue;
-      int pi[3], nat[8];
-      double sg[3];
-      decode(orient[c], pi, sg);
-      for (int k = 0; k < 8; ++k) nat[corner_image(k, pi, sg)] = iconn[cptr[c] + k];
-      for (int k = 0; k < 8; ++k) iconn[cptr[c] + k] = nat[k];
-      orient[c] = 0;
-    }
-  }
+  const int64_t ndof = P.ndof;
 
   auto* m = new sbfem_mesh();
   m->alloc = g_alloc;
   m->P = p;
   (void)hipGetDevice(&m->device);
-  m->N = N;
-  m->C = C;
+  m->N = P.N;
+  m->C = P.C;
   m->ndof = ndof;
   m->h0 = d->h0;
   m->dt = d->dt;
@@ -758,393 +1189,80 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   m->L.cycles = d->load_cycles;
   m->L.t1 = d->load_t1;
   m->L.P0 = d->load_P0;
-
-  // lumped diagonal mass in internal numbering (summation order fixed: cell order)
-  std::vector<double> mdiag(ndof, 0.0);
-  for (int64_t c = 0; c < C; ++c) {
-    const int pid = d->pattern[c];
-    const double h = std::ldexp(d->h0, -(int)d->level[c]);
-    const double sc = d->rho[d->material[c]] * h * h * h;
-    int pi[3];
-    double sg[3];
-    decode(orient[c], pi, sg);
-    const double* mp = p->m.data() + p->moff[pid];
-    for (int64_t k = 0; k < cptr[c + 1] - cptr[c]; ++k)
-      for (int a = 0; a < 3; ++a) mdiag[3 * (int64_t)iconn[cptr[c] + k] + pi[a]] += sc * mp[3 * k + a];
-  }
-  std::vector<double> minv(ndof);
-  for (int64_t i = 0; i < ndof; ++i) {
-    const int64_t e = 3 * (int64_t)int2ext[i / 3] + i % 3;
-    const bool fixed = d->fixed_dof && d->fixed_dof[e];
-    if (fixed) {
-      minv[i] = 0.0;
-    } else {
-      if (!(mdiag[i] > 0)) {
-        sbfem_destroy_mesh(m);
-        return fail(SBFEM_EINVAL, "free dof %lld has no mass (node not used by any cell?)", (long long)e);
-      }
-      minv[i] = 1.0 / mdiag[i];
-    }
-  }
-
-  // load vector (internal dofs) with merged duplicates
-  std::map<int64_t, double> bmap;
-  for (int64_t i = 0; i < d->load_nnz; ++i) {
-    if (d->load_dof[i] < 0 || d->load_dof[i] >= ndof) {
-      sbfem_destroy_mesh(m);
-      return fail(SBFEM_EINVAL, "load dof %lld out of range", (long long)d->load_dof[i]);
-    }
-    const int64_t e = d->load_dof[i];
-    bmap[3 * (int64_t)ext2int[e / 3] + e % 3] += d->load_val[i];
-  }
-  std::vector<int64_t> bidx;
-  std::vector<double> bval;
-  for (auto& kv : bmap) {
-    bidx.push_back(kv.first);
-    bval.push_back(kv.second);
-  }
-  m->nnz = (int64_t)bidx.size();
-
-  std::vector<double> matE(256, 0.0);
-  for (int i = 0; i < d->n_materials; ++i) matE[i] = d->E[i];
+  m->nnz = (int64_t)P.bidx.size();
+  m->n_colours = P.n_colours;
+  m->groups = P.groups;
+  m->n_pure8 = P.to.n_pure8;
+  m->n_mixed = P.to.n_mixed;
+  m->tile_nodes = P.to.tile_nodes;
+  m->halo_stride = P.to.halo_stride;
+  m->n_hang = (int64_t)P.hitems.size();
+  m->lds_hang = P.lds_hang;
+  m->lds_bytes = P.lds_bytes;
+  m->block_threads = P.block_threads;
+  m->block_threads_mixed = P.block_threads_mixed;
+  m->walsh = P.walsh;
+  m->hang_mma = P.hang_mma;
+  for (int i = 0; i < 10; ++i) m->layout[i] = P.layout[i];
 
   hipError_t e = hipSuccess;
-  auto H2D = [&](void* dst, const void* src, size_t bytes) {
-    if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
-  };
   int64_t bytes = 0;
-#define ALLOC(ptr, n)                                            \
-  if (e == hipSuccess) {                                         \
-    e = dalloc(m->alloc, &m->ptr, (size_t)(n));                            \
-    bytes += (int64_t)(n) * (int64_t)sizeof(*m->ptr);            \
-  }
-  // state storage u, u_prev (and M^-1: FP32 with FP32 state, else FP64)
-  const int64_t sbytes = state_bytes(d->state, ndof);
-  const int64_t mbytes = ndof * (d->state == SBFEM_STATE_FP32 ? 4 : 8);
-  if (e == hipSuccess) e = dalloc_bytes(m->alloc, &m->u, sbytes);
-  if (e == hipSuccess) e = dalloc_bytes(m->alloc, &m->um1, sbytes);
-  if (e == hipSuccess) e = dalloc_bytes(m->alloc, &m->minv, mbytes);
-  bytes += 2 * sbytes + mbytes;
-  ALLOC(f, ndof)
-  ALLOC(matE, 256)
-  ALLOC(flag_d, 1)
-
+  for_each_buffer(P, d, m, [&](void** slot, size_t b) {
+    if (e == hipSuccess) e = dalloc_bytes(m->alloc, slot, b);
+    bytes += (int64_t)b;
+  });
+  m->bytes = bytes;
+  auto H2D = [&](void* dst, const void* src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+  };
   if (d->assembly == SBFEM_ASM_TILED) {
-    sbfem::TilingInput ti;
-    ti.n_nodes = N;
-    ti.n_cells = C;
-    ti.cptr = cptr.data();
-    ti.conn = iconn.data();
-    ti.pattern = d->pattern;
-    ti.orient = orient.data();
-    ti.level = d->level;
-    ti.material = d->material;
-    ti.pattern_ndof = p->ndof.data();
-    ti.pattern_koff = p->koff.data();
-    ti.load_dof = bidx;
-    ti.load_val = bval;
-    sbfem::TilingOutput to;
-    // tile size: env SBFEM_TILE_NODES or the default; halved until one block's LDS
-    // (u of its local nodes + f of its owned ones) fits the per-block limit
-    int lds_max = 65536;
-    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
-    if (lds_max < 16384) lds_max = 65536;
-    int32_t tn0 = kOwnerTileNodes;
-    if (const char* ev = std::getenv("SBFEM_TILE_NODES")) tn0 = std::max(32, std::atoi(ev));
-    auto threads_env = [](const char* name, int32_t& v) {
-      if (const char* ev = std::getenv(name)) {
-        const int bt = std::atoi(ev);
-        if (bt >= 64 && bt <= 512 && bt % 64 == 0) v = bt;
-      }
-    };
-    threads_env("SBFEM_BLOCK_THREADS", m->block_threads);
-    threads_env("SBFEM_BLOCK_THREADS_MIXED", m->block_threads_mixed);
-    // explicit descriptor values win over the defaults and the environment
-    auto threads_desc = [](int32_t v, int32_t& out) {
-      if (v >= 64 && v <= 512 && v % 64 == 0) out = v;
-    };
-    threads_desc(d->block_threads, m->block_threads);
-    threads_desc(d->block_threads_mixed, m->block_threads_mixed);
-    if (d->tile_nodes > 0) tn0 = std::max(32, d->tile_nodes);
-    if (const char* ev = std::getenv("SBFEM_DENSE8")) m->walsh = std::atoi(ev) == 0;
-    ti.p8 = m->walsh ? p->p8 : -1;
-    bool ok = false;
-    // LDS per block: FP64 forces of the owned nodes, u of the local nodes (FP64: 24 B per node;
-    // FP32: 12 B, 16 B in pure 8-node tiles)
-    const int64_t node_bytes = d->prod != SBFEM_PROD_FP64 ? 16 : 24;
-    for (int32_t tn = tn0; tn >= 32; tn /= 2) {
-      if (sbfem::build_owner_tiles(ti, tn, to) && node_bytes * to.max_local + 24 * to.tile_nodes <= lds_max) {
-        m->lds_bytes = (int32_t)(node_bytes * to.max_local + 24 * to.tile_nodes);
-        ok = true;
-        break;
-      }
-    }
-    if (!ok) {
-      sbfem_destroy_mesh(m);
-      return fail(SBFEM_EINVAL, "no owner-tile size fits the on-chip memory of a block");
-    }
-    m->n_pure8 = to.n_pure8;
-    m->n_mixed = to.n_mixed;
-    m->tile_nodes = to.tile_nodes;
-    // hanging-node cells (every cell that is not a regular 8-node cell), each once: items of up
-    // to a wave of cells of one pattern, in cell order within a pattern; node ids slot-major
-    std::vector<int64_t> hcells;
-    for (int64_t c = 0; c < C; ++c)
-      if (ti.p8 < 0 || d->pattern[c] != ti.p8) hcells.push_back(c);
-    std::stable_sort(hcells.begin(), hcells.end(),
-                     [&](int64_t x, int64_t y) { return d->pattern[x] < d->pattern[y]; });
-    std::vector<sbfem::HangItem> hitems;
-    std::vector<int32_t> hconn;
-    std::vector<uint8_t> hor, hlev, hmat;
-    // the items of one hanging-pass block share a pattern: each pattern's items are padded with
-    // empty items to whole blocks; the block stages that pattern's matrix in LDS
-    const int per_block = m->block_threads_mixed / sbfem::kWave;
-    int64_t n_res = 0;  // result slots: 64 per row of every item
-    std::vector<std::pair<int64_t, sbfem::HangPair>> tpairs;  // (tile, pair)
-    int64_t kl_max = 0;  // entries of the largest staged matrix (rows padded to 4)
-    for (size_t i0 = 0; i0 < hcells.size();) {
-      const int pid = d->pattern[hcells[i0]];
-      size_t i1 = i0;
-      while (i1 < hcells.size() && i1 - i0 < (size_t)sbfem::kWave && d->pattern[hcells[i1]] == pid) ++i1;
-      sbfem::HangItem it{};
-      it.res0 = n_res;
-      it.cell0 = (int64_t)hor.size();
-      it.conn0 = (int64_t)hconn.size();
-      it.koff = p->koff[pid];
-      it.nn = p->ndof[pid] / 3;
-      it.count = (int32_t)(i1 - i0);
-      for (int k = 0; k < it.nn; ++k)
-        for (size_t j = i0; j < i1; ++j) hconn.push_back(iconn[cptr[hcells[j]] + k]);
-      for (size_t j = i0; j < i1; ++j) {
-        hor.push_back(orient[hcells[j]]);
-        hlev.push_back(d->level[hcells[j]]);
-        hmat.push_back(d->material[hcells[j]]);
-      }
-      hitems.push_back(it);
-      const int64_t nd = p->ndof[pid];
-      // row r of lane j: dof 3 g_k + pi(a) (r = 3k + a) of the tile that owns node g_k
-      for (size_t j = i0; j < i1; ++j) {
-        const int64_t c = hcells[j];
-        int pi[3];
-        double sg[3];
-        decode(orient[c], pi, sg);
-        for (int r = 0; r < nd; ++r) {
-          const int64_t g = iconn[cptr[c] + r / 3];
-          const int64_t t = g / to.tile_nodes;
-          const int64_t ri = n_res + (int64_t)r * sbfem::kWave + (int64_t)(j - i0);
-          tpairs.push_back({t, {(int32_t)(3 * (g - t * to.tile_nodes) + pi[r % 3]), (uint32_t)ri}});
-        }
-      }
-      n_res += nd * sbfem::kWave;
-      kl_max = std::max<int64_t>(kl_max, nd * ((nd + 3) & ~3));
-      i0 = i1;
-      if (i0 == hcells.size() || d->pattern[hcells[i0]] != pid) {
-        sbfem::HangItem pad = it;
-        pad.count = 0;
-        while (hitems.size() % per_block) hitems.push_back(pad);
-      }
-    }
-    m->n_hang = (int64_t)hitems.size();
-    m->lds_hang = kl_max * (d->prod == SBFEM_PROD_FP64 ? 8 : 4);
-    if (n_res > (int64_t)UINT32_MAX) {
-      sbfem_destroy_mesh(m);
-      return fail(SBFEM_EINVAL, "too many hanging-node cells for 32-bit result indices");
-    }
-    // pairs grouped by owner tile (each tile's pairs in result order)
-    std::stable_sort(tpairs.begin(), tpairs.end(),
-                     [](const auto& x, const auto& y) { return x.first < y.first; });
-    std::vector<sbfem::HangPair> hpairs(tpairs.size());
-    for (size_t i = 0; i < tpairs.size(); ++i) {
-      hpairs[i] = tpairs[i].second;
-      auto& ot = to.tiles[tpairs[i].first];
-      if (ot.n_hpair == 0) ot.hpair0 = (int64_t)i;
-      ot.n_hpair++;
-    }
-    std::vector<std::pair<int64_t, sbfem::HangPair>>().swap(tpairs);
-    m->layout[0] = to.n_pure8;
-    m->layout[1] = to.n_mixed;
-    m->layout[2] = (int64_t)to.items.size();
-    m->layout[3] = to.local_entries;
-    m->halo_stride = to.halo_stride;
-    m->layout[4] = (int64_t)hcells.size();  // regular cell entries over all tiles, plus the hanging cells
-    for (const auto& it : to.items) m->layout[4] += it.count;
-    m->layout[5] = to.tile_nodes;
-    // algorithmic bytes per step of each pass (the method's own traffic, whatever the layout):
-    // the owner-tile pass reads u_n, u_{n-1}, M^-1 and writes u_{n+1} of every dof (8 B each),
-    // the node ids (4 B each) and orientation, level, material (1 B each) of the regular
-    // 8-node cells, and the load entries (16 B); the hanging-cell pass the same per-cell
-    // bytes of the other cells
-    {
-      int64_t b8 = 32 * ndof + 16 * (int64_t)bidx.size(), bo = 0;
-      for (int64_t c = 0; c < C; ++c)
-        (ti.p8 >= 0 && d->pattern[c] == ti.p8 ? b8 : bo) += 4 * (cptr[c + 1] - cptr[c]) + 3;
-      m->layout[6] = b8;
-      m->layout[7] = bo;
-    }
-    m->layout[8] = to.max_local;
-    m->layout[9] = m->lds_bytes;
-    ALLOC(otiles, to.tiles.size())
-    ALLOC(items, to.items.size())
-    ALLOC(lidx, to.lidx.size())
-    ALLOC(nodelist, to.nodelist.size())
-    ALLOC(tloads, to.loads.size())
-    ALLOC(hitems, hitems.size())
-    ALLOC(hconn, hconn.size())
-    ALLOC(horient, hor.size())
-    ALLOC(hlevel, hlev.size())
-    ALLOC(hmaterial, hmat.size())
-    ALLOC(hpairs, std::max<size_t>(1, hpairs.size()))
-    ALLOC(hres, std::max<int64_t>(1, n_res))
-    ALLOC(d_args, 2)
-    ALLOC(d_ref, 1)
-    H2D(m->hitems, hitems.data(), hitems.size() * sizeof(sbfem::HangItem));
-    H2D(m->hconn, hconn.data(), hconn.size() * 4);
-    H2D(m->horient, hor.data(), hor.size());
-    H2D(m->hlevel, hlev.data(), hlev.size());
-    H2D(m->hmaterial, hmat.data(), hmat.size());
-    H2D(m->hpairs, hpairs.data(), hpairs.size() * sizeof(sbfem::HangPair));
-    // structured Walsh table pre-multiplied by s_e = E h of each scale class (one rounding per entry)
-    const size_t ncls = to.scale_keys.size();
-    const int WC = sbfem::kWalshC;
-    std::vector<double> ws64(std::max<size_t>(1, ncls) * WC, 0.0);
-    std::vector<float> ws32(ws64.size(), 0.0f);
-    for (size_t c = 0; c < ncls; ++c) {
-      const int lev = to.scale_keys[c] >> 8, mat = to.scale_keys[c] & 255;
-      const double se = d->E[mat] * std::ldexp(d->h0, -lev);
-      for (int i = 0; i < WC; ++i) {
-        ws64[WC * c + i] = se * p->Wc[i];
-        ws32[WC * c + i] = (float)ws64[WC * c + i];
-      }
-      if (d->prod == SBFEM_PROD_FP16 || d->prod == SBFEM_PROD_BF16) {
-        // 16-bit operands: the unscaled coefficients rounded to 16 bits, s_e applied after
-        for (int i = 0; i < WC - 1; ++i)
-          ws32[WC * c + i] = d->prod == SBFEM_PROD_FP16 ? round_fp16((float)p->Wc[i]) : round_bf16((float)p->Wc[i]);
-        ws32[WC * c + WC - 1] = (float)se;
-      }
-    }
-    ALLOC(dWs64, ws64.size())
-    ALLOC(dWs32, ws32.size())
-    H2D(m->dWs64, ws64.data(), ws64.size() * 8);
-    H2D(m->dWs32, ws32.data(), ws32.size() * 4);
+    const auto& to = P.to;
     H2D(m->otiles, to.tiles.data(), to.tiles.size() * sizeof(sbfem::OwnerTile));
     H2D(m->items, to.items.data(), to.items.size() * sizeof(sbfem::CellItem));
     H2D(m->lidx, to.lidx.data(), to.lidx.size() * 2);
     H2D(m->nodelist, to.nodelist.data(), to.nodelist.size() * 4);
     H2D(m->tloads, to.loads.data(), to.loads.size() * sizeof(sbfem::LoadEntry));
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers of `to` die below
+    H2D(m->hitems, P.hitems.data(), P.hitems.size() * sizeof(sbfem::HangItem));
+    H2D(m->hconn, P.hconn.data(), P.hconn.size() * 4);
+    H2D(m->horient, P.hor.data(), P.hor.size());
+    H2D(m->hlevel, P.hlev.data(), P.hlev.size());
+    H2D(m->hmaterial, P.hmat.data(), P.hmat.size());
+    H2D(m->hpairs, P.hpairs.data(), P.hpairs.size() * sizeof(sbfem::HangPair));
+    H2D(m->dWs64, P.ws64.data(), P.ws64.size() * 8);
+    H2D(m->dWs32, P.ws32.data(), P.ws32.size() * 4);
   } else {
-    // colours: greedy in input order, per-node mask of the colours already touching it
-    std::vector<uint8_t> colour(C, 0);
-    int n_colours = 1;
-    if (d->assembly == SBFEM_ASM_COLOUR) {
-      std::vector<uint64_t> used(N, 0);
-      for (int64_t c = 0; c < C; ++c) {
-        uint64_t forb = 0;
-        for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) forb |= used[iconn[i]];
-        if (forb == ~0ull) {
-          sbfem_destroy_mesh(m);
-          return fail(SBFEM_EINVAL, "cell %lld needs more than 64 colours", (long long)c);
-        }
-        int col = 0;
-        while ((forb >> col) & 1) ++col;
-        colour[c] = (uint8_t)col;
-        n_colours = std::max(n_colours, col + 1);
-        for (int64_t i = cptr[c]; i < cptr[c + 1]; ++i) used[iconn[i]] |= 1ull << col;
-      }
-    }
-    m->n_colours = n_colours;
-    // order: colour, 8-node class first, pattern; stable in input order (counting sort)
-    const int64_t n_keys = (int64_t)n_colours * 2 * p->n;
-    auto key = [&](int64_t c) -> int64_t {
-      const int pid = d->pattern[c];
-      const int mixed = p->ndof[pid] == 24 ? 0 : 1;
-      return ((int64_t)colour[c] * 2 + mixed) * p->n + pid;
-    };
-    std::vector<int64_t> order(C);
-    {
-      std::vector<int64_t> start(n_keys + 1, 0);
-      for (int64_t c = 0; c < C; ++c) start[key(c) + 1]++;
-      for (int64_t k = 0; k < n_keys; ++k) start[k + 1] += start[k];
-      for (int64_t c = 0; c < C; ++c) order[start[key(c)]++] = c;
-    }
-    // segments, tiles and slot-major node ids
-    std::vector<int32_t> sconn(total);
-    std::vector<uint8_t> sorient(C), slevel(C), smat(C);
-    std::vector<sbfem::Tile> tiles;
-    m->groups.assign(n_colours, sbfem::TileRange{-1, 0, 0});
-    int64_t cpos = 0, i0 = 0;
-    while (i0 < C) {
-      int64_t i1 = i0;
-      const int64_t k0 = key(order[i0]);
-      while (i1 < C && key(order[i1]) == k0) ++i1;
-      const int pid = d->pattern[order[i0]];
-      const int nn = p->ndof[pid] / 3;
-      const int col = colour[order[i0]];
-      const int64_t cnt = i1 - i0;
-      for (int64_t j = 0; j < cnt; ++j) {
-        const int64_t c = order[i0 + j];
-        for (int k = 0; k < nn; ++k) sconn[cpos + (int64_t)k * cnt + j] = iconn[cptr[c] + k];
-        sorient[i0 + j] = orient[c];
-        slevel[i0 + j] = d->level[c];
-        smat[i0 + j] = d->material[c];
-      }
-      auto& g = m->groups[col];
-      if (g.first < 0) g.first = (int64_t)tiles.size();
-      for (int64_t j = 0; j < cnt; j += sbfem::kTile) {
-        sbfem::Tile t;
-        t.cell0 = i0 + j;
-        t.conn0 = cpos + j;
-        t.stride = cnt;
-        t.koff = p->koff[pid];
-        t.count = (int32_t)std::min<int64_t>(sbfem::kTile, cnt - j);
-        t.nn = nn;
-        tiles.push_back(t);
-        if (nn == 8)
-          g.n_fixed8++;
-        else
-          g.n_mixed++;
-      }
-      cpos += cnt * nn;
-      i0 = i1;
-    }
-    for (auto& g : m->groups)
-      if (g.first < 0) g.first = 0;
-    ALLOC(conn, total)
-    ALLOC(orient, C)
-    ALLOC(level, C)
-    ALLOC(material, C)
-    ALLOC(tiles, tiles.size())
-    ALLOC(load_idx, m->nnz)
-    ALLOC(load_val, m->nnz)
-    H2D(m->conn, sconn.data(), total * 4);
-    H2D(m->orient, sorient.data(), C);
-    H2D(m->level, slevel.data(), C);
-    H2D(m->material, smat.data(), C);
-    H2D(m->tiles, tiles.data(), tiles.size() * sizeof(sbfem::Tile));
-    H2D(m->load_idx, bidx.data(), m->nnz * 8);
-    H2D(m->load_val, bval.data(), m->nnz * 8);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    H2D(m->conn, P.sconn.data(), P.sconn.size() * 4);
+    H2D(m->orient, P.sorient.data(), P.sorient.size());
+    H2D(m->level, P.slevel.data(), P.slevel.size());
+    H2D(m->material, P.smat.data(), P.smat.size());
+    H2D(m->tiles, P.tiles.data(), P.tiles.size() * sizeof(sbfem::Tile));
+    H2D(m->load_idx, P.bidx.data(), P.bidx.size() * 8);
+    H2D(m->load_val, P.bval.data(), P.bval.size() * 8);
   }
-#undef ALLOC
-  m->bytes = bytes;
-  if (e == hipSuccess) e = hipHostMalloc((void**)&m->flag_h, sizeof(int32_t), hipHostMallocDefault);
+  if (d->assembly == SBFEM_ASM_TILED) {
+    if (d->state == SBFEM_STATE_FP32) {
+      H2D(m->minv, P.mnode32.data(), P.mnode32.size() * 4);
+      H2D(m->minv_exc, P.mexc32.data(), P.mexc32.size() * 4);
+    } else {
+      H2D(m->minv, P.mnode64.data(), P.mnode64.size() * 8);
+      H2D(m->minv_exc, P.mexc64.data(), P.mexc64.size() * 8);
+    }
+  } else {
+    H2D(m->minv, P.minv.data(), ndof * 8);
+  }
+  H2D(m->matE, P.matE.data(), 256 * 8);
+  const unsigned long long no_flag = ~0ull;
+  H2D(m->flag_d, &no_flag, sizeof(no_flag));
+  if (e == hipSuccess && m->f) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&m->flag_h, sizeof(unsigned long long), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&m->flag_ev, hipEventDisableTiming);
-  std::vector<float> minv32;
-  if (d->state == SBFEM_STATE_FP32) {
-    minv32.assign(minv.begin(), minv.end());
-    H2D(m->minv, minv32.data(), ndof * 4);
-  } else {
-    H2D(m->minv, minv.data(), ndof * 8);
-  }
-  H2D(m->matE, matE.data(), 256 * 8);
-  if (e == hipSuccess) e = hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s);
-  if (e == hipSuccess) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the plan's host buffers die with this call
   if (e != hipSuccess) {
     sbfem_destroy_mesh(m);
     return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "create_mesh upload: %s",
                 hipGetErrorString(e));
   }
-  *m->flag_h = 0;
+  *m->flag_h = no_flag;
   m->buf0 = m->u;
   if (d->assembly == SBFEM_ASM_TILED) {
     const sbfem::TiledArgs ta[2] = {tiled_args_for(m, m->u, m->um1), tiled_args_for(m, m->um1, m->u)};
@@ -1153,9 +1271,10 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   }
 
   // start-up point (eq. D0): u_-1 = u0 - dt v0 + dt^2/2 a0,  a0 = M^-1 (P(0) b - K u0) - alpha v0
+  const std::vector<double>& minv = P.minv;
   std::vector<double> u0(ndof, 0.0), v0(ndof, 0.0), ku0(ndof, 0.0);
   for (int64_t i = 0; i < ndof; ++i) {
-    const int64_t ex = 3 * (int64_t)int2ext[i / 3] + i % 3;
+    const int64_t ex = 3 * (int64_t)P.int2ext[i / 3] + i % 3;
     if (d->u0) u0[i] = d->u0[ex];
     if (d->v0) v0[i] = d->v0[ex];
     if (minv[i] == 0.0) u0[i] = v0[i] = 0.0;
@@ -1175,7 +1294,7 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   const double P0t = load_time_host(m->L, 0.0);
   std::vector<double> um1(ndof);
   std::vector<double> fext(ndof, 0.0);
-  for (size_t i = 0; i < bidx.size(); ++i) fext[bidx[i]] = P0t * bval[i];
+  for (size_t i = 0; i < P.bidx.size(); ++i) fext[P.bidx[i]] = P0t * P.bval[i];
   for (int64_t i = 0; i < ndof; ++i) {
     const double a0 = minv[i] * (fext[i] - ku0[i]) - (minv[i] != 0.0 ? d->alpha * v0[i] : 0.0);
     um1[i] = u0[i] - d->dt * v0[i] + 0.5 * d->dt * d->dt * a0;
@@ -1187,9 +1306,26 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     sbfem_destroy_mesh(m);
     return fail(SBFEM_EDEVICE, "create_mesh initial state: %s", hipGetErrorString(e));
   }
-  m->int2ext.swap(int2ext);
-  m->mdiag.swap(mdiag);
+  m->int2ext.swap(P.int2ext);
+  m->mdiag.swap(P.mdiag);
   *out = m;
+  return SBFEM_OK;
+}
+
+// The FP64 force array over all dofs, allocated on first use by a mesh that has none (the
+// owner-tile step needs none; the force-only evaluation writes it).
+static sbfem_status ensure_force_array(sbfem_mesh* m, hipStream_t s) {
+  if (m->f) return SBFEM_OK;
+  HIP_TRY(dalloc(m->alloc, &m->f, (size_t)m->ndof));
+  m->bytes += m->ndof * 8;
+  if (m->assembly == SBFEM_ASM_TILED) {
+    const bool swapped = m->u != m->buf0;
+    void* b0 = m->buf0;
+    void* b1 = swapped ? m->u : m->um1;
+    const sbfem::TiledArgs ta[2] = {tiled_args_for(m, b0, b1), tiled_args_for(m, b1, b0)};
+    HIP_TRY(hipMemcpyAsync(m->d_args, ta, sizeof(ta), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   return SBFEM_OK;
 }
 
@@ -1199,7 +1335,9 @@ static sbfem_status check_flag(sbfem_mesh* m) {
   if (q == hipErrorNotReady) return SBFEM_OK;
   m->flag_pending = false;
   if (q != hipSuccess) return fail(SBFEM_EDEVICE, "finite check: %s", hipGetErrorString(q));
-  if (*m->flag_h) return fail(SBFEM_EUNSTABLE, "displacement became non-finite (time step above the stability limit?)");
+  if (*m->flag_h != ~0ull)
+    return fail(SBFEM_EUNSTABLE, "displacement became non-finite at step %llu (time step above the stability limit?)",
+                *m->flag_h + 1);
   return SBFEM_OK;
 }
 
@@ -1220,19 +1358,17 @@ static sbfem_status enqueue_step(sbfem_mesh* m, hipStream_t s) {
   if (st != SBFEM_OK) return st;
   h(3, true, s);
   HIP_TRY(sbfem::launch_update((const double*)m->u, (double*)m->um1, m->f, (const double*)m->minv, m->ndof,
-                               m->dt * m->dt, 0.5 * m->alpha * m->dt, s));
+                               m->dt * m->dt, 0.5 * m->alpha * m->dt, m->flag_d, m->step, s));
   h(3, false, s);
   std::swap(m->u, m->um1);
   m->step++;
   return SBFEM_OK;
 }
 
+// The update kernels record the first step whose result is not finite; its value is copied
+// to the host behind the call's work and examined by the next call on the mesh.
 static sbfem_status finish_steps(sbfem_mesh* m, hipStream_t s) {
-  if (m->state_mode == SBFEM_STATE_FP64)
-    HIP_TRY(sbfem::launch_finite((const double*)m->u, m->ndof, m->flag_d, s));
-  else  // FP32 values, or the high parts of compensated pairs
-    HIP_TRY(sbfem::launch_finite32((const float*)m->u, m->ndof, m->flag_d, s));
-  HIP_TRY(hipMemcpyAsync(m->flag_h, m->flag_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(m->flag_h, m->flag_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipEventRecord(m->flag_ev, s));
   m->flag_pending = true;
   return SBFEM_OK;
@@ -1475,7 +1611,8 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
       if (!used[j] && ms[j]->assembly == SBFEM_ASM_TILED && !ms[j]->profiling && ms[j]->P == ms[i]->P &&
           ms[j]->prod == ms[i]->prod && ms[j]->state_mode == ms[i]->state_mode &&
           ms[j]->block_threads == ms[i]->block_threads &&
-          ms[j]->block_threads_mixed == ms[i]->block_threads_mixed && n_steps[j] > 0) {
+          ms[j]->block_threads_mixed == ms[i]->block_threads_mixed && ms[j]->hang_mma == ms[i]->hang_mma &&
+          n_steps[j] > 0) {
         g.push_back(ms[j]);
         st.push_back(n_steps[j]);
         used[j] = 1;
@@ -1513,7 +1650,9 @@ sbfem_status sbfem_read_state(sbfem_mesh* m, int32_t which, double* host_out, in
   if (which == 3) {
     tmp = m->mdiag;
   } else if (which == 2) {
-    sbfem_status st = internal_force(m, s);
+    sbfem_status st = ensure_force_array(m, s);
+    if (st != SBFEM_OK) return st;
+    st = internal_force(m, s);
     if (st != SBFEM_OK) return st;
     HIP_TRY(hipMemcpyAsync(tmp.data(), m->f, m->ndof * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(sbfem::launch_fill(m->f, m->ndof, 0.0, s));
@@ -1545,10 +1684,12 @@ sbfem_status sbfem_write_state(sbfem_mesh* m, const double* u_n, const double* u
   const std::vector<char> rb = pack_state(m->state_mode, b.data(), m->ndof);
   HIP_TRY(hipMemcpyAsync(m->u, ra.data(), ra.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(m->um1, rb.data(), rb.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(m->flag_d, 0, sizeof(int32_t), s));
+  const unsigned long long no_flag = ~0ull;
+  HIP_TRY(hipMemcpyAsync(m->flag_d, &no_flag, sizeof(no_flag), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   m->step = step;
   m->flag_pending = false;
+  *m->flag_h = no_flag;
   return SBFEM_OK;
 }
 

@@ -155,16 +155,10 @@ __device__ __forceinline__ uint4 cell8_record(const TiledArgs& a, const CellItem
   return load_global(as_global(reinterpret_cast<const uint4*>(a.lidx)) + ((it.lidx0 >> 3) + lane));
 }
 
-// A regular 8-node cell: gather from the staged u (FP32: 16-byte float4 nodes, FP64: 3
-// doubles), structured Walsh product with the class-scaled table, FP64 LDS atomics into the
-// rows of owned corners.
-template <bool FP32, bool RED>
-__device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, const uint4 q, int n_own,
-                                      const typename LdsType<FP32>::T* __restrict__ ul, double* __restrict__ fl);
-
-// Precision forms: kernels instantiated with RED = false take FP64 state and no 16-bit
-// rounding as compile-time constants (the plain and mixed paths); RED = true reads them from
-// the argument block.
+// Precision forms of the hanging-cell pass with one lane per cell: kernels instantiated with
+// RED = false take FP64 state and no 16-bit rounding as compile-time constants; RED = true
+// reads them from the argument block.  (The owner-tile pass and the matrix-core hanging pass
+// take the product precision and the state storage as template parameters.)
 template <bool RED>
 __device__ __forceinline__ int32_t state_of(const TiledArgs& a) {
   return RED ? a.state : 0;
@@ -174,7 +168,17 @@ __device__ __forceinline__ int32_t round_of(const TiledArgs& a) {
   return RED ? a.round16 : 0;
 }
 
-template <bool FP32, bool RED>
+// product precision (sbfem_prod) -> 16-bit operand rounding of the Walsh product (0 none,
+// 1 FP16, 2 BF16)
+template <int PROD>
+__host__ __device__ constexpr int round_mode() {
+  return PROD == 2 ? 1 : (PROD == 3 ? 2 : 0);
+}
+
+// A regular 8-node cell: gather from the staged u (FP32: 16-byte float4 nodes, FP64: 3
+// doubles), structured Walsh product with the class-scaled table, FP64 LDS atomics into the
+// rows of owned corners.
+template <bool FP32, int RM>
 __device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, const uint4 q, int n_own,
                                       const typename LdsType<FP32>::T* __restrict__ ul, double* __restrict__ fl) {
   using T = typename LdsType<FP32>::T;
@@ -195,7 +199,7 @@ __device__ __forceinline__ void cell8(const TiledArgs& a, const CellItem& it, co
     }
   }
   T fe[24];
-  walsh8_sym<T>(as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64) + it.koff, ue, fe, round_of<RED>(a));
+  walsh8_sym<T>(as_const(FP32 ? (const T*)a.Ws32 : (const T*)a.Ws64) + it.koff, ue, fe, RM);
   const uint32_t mask = it.mask;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -244,51 +248,131 @@ __device__ __forceinline__ void tile_loads(const TiledArgs& a, const OwnerTile& 
   }
 }
 
-// Forces of hanging-node cells on the tile's owned dofs, from the hanging-cell pass.
+// Forces of hanging-node cells on the tile's owned dofs, from the hanging-cell pass (stored
+// in FP64 for FP64 products, else in FP32).
+template <bool FP32>
 __device__ __forceinline__ void tile_hang_forces(const TiledArgs& a, const OwnerTile& tile, double* fl, int tid,
                                                  int nt) {
+  using RT = typename LdsType<FP32>::T;
   const gptr_t<HangPair> pr = as_global(a.hpairs) + tile.hpair0;
-  const gptr_t<double> res = as_global((const double*)a.hres);
+  const gptr_t<RT> res = as_global((const RT*)a.hres);
   for (int i = tid; i < tile.n_hpair; i += nt) {
     const HangPair h = load_global(pr + i);
-    atomicAdd(fl + h.ldof, res[h.res]);
+    atomicAdd(fl + h.ldof, (double)res[h.res]);
   }
 }
 
-// Central-difference update of the owned dofs written over u_{n-1} (or R_int, force-only),
-// after adding and clearing the tile's partial forces.  un_lds: u_n of the owned dofs as
-// staged (FP64 staging holds u_n itself).
-template <bool FP32, bool RED>
+// Inverse lumped mass of an owned node (owner-tile layout): one value per node (FP64, FP32 with
+// FP32 state); a node whose three values differ (masses of hanging-node cells, a partly fixed
+// node) has the sign bit set and, in the other bits, 1 + its position in a table of three values
+// per such node.  Fixed dofs have the value 0 (eq. DnMdiag then keeps them at rest).
+template <int STATE>
+struct MinvRaw {
+  using T = uint64_t;
+};
+template <>
+struct MinvRaw<1> {
+  using T = uint32_t;
+};
+template <int STATE>
+__device__ __forceinline__ typename MinvRaw<STATE>::T minv_raw(const TiledArgs& a, int64_t node) {
+  using R = typename MinvRaw<STATE>::T;
+  return as_global((const R*)a.minv)[node];
+}
+template <int STATE>
+__device__ __forceinline__ void minv_decode(const TiledArgs& a, typename MinvRaw<STATE>::T raw, double& m0,
+                                            double& m1, double& m2) {
+  using R = typename MinvRaw<STATE>::T;
+  constexpr R sign = R(1) << (8 * sizeof(R) - 1);
+  if (raw & sign) {
+    const int64_t x = 3 * ((int64_t)(raw & ~sign) - 1);
+    if constexpr (STATE == 1) {
+      const gptr_t<float> e = as_global((const float*)a.minv_exc) + x;
+      m0 = e[0], m1 = e[1], m2 = e[2];
+    } else {
+      const gptr_t<double> e = as_global((const double*)a.minv_exc) + x;
+      m0 = e[0], m1 = e[1], m2 = e[2];
+    }
+  } else {
+    if constexpr (STATE == 1)
+      m0 = (double)__uint_as_float((uint32_t)raw);
+    else
+      m0 = __longlong_as_double((long long)raw);
+    m1 = m2 = m0;
+  }
+}
+
+// the inverse mass of component comp of the node whose raw value this is
+template <int STATE>
+__device__ __forceinline__ double minv_of_dof(const TiledArgs& a, typename MinvRaw<STATE>::T raw, int comp) {
+  using R = typename MinvRaw<STATE>::T;
+  constexpr R sign = R(1) << (8 * sizeof(R) - 1);
+  if (raw & sign) {
+    const int64_t x = 3 * ((int64_t)(raw & ~sign) - 1) + comp;
+    if constexpr (STATE == 1)
+      return (double)as_global((const float*)a.minv_exc)[x];
+    else
+      return as_global((const double*)a.minv_exc)[x];
+  }
+  if constexpr (STATE == 1)
+    return (double)__uint_as_float((uint32_t)raw);
+  else
+    return __longlong_as_double((long long)raw);
+}
+
+// u_{n+1} of one owned node from its forces, u_n, u_{n-1} and inverse mass (eq. DnMdiag),
+// written over u_{n-1}; false if a stored value is not finite
+template <int STATE>
+__device__ __forceinline__ bool node_update(const TiledArgs& a, int64_t node, const double* f, double un0, double un1,
+                                            double un2, double up0, double up1, double up2, double m0, double m1,
+                                            double m2) {
+  const double inv = 1.0 / (1.0 + a.c), cm = 1.0 - a.c;
+  const double v0 = (a.dt2 * m0 * (-f[0]) + 2.0 * un0 - cm * up0) * inv;
+  const double v1 = (a.dt2 * m1 * (-f[1]) + 2.0 * un1 - cm * up1) * inv;
+  const double v2 = (a.dt2 * m2 * (-f[2]) + 2.0 * un2 - cm * up2) * inv;
+  state_store(a.um1, STATE, a.ndof, 3 * node + 0, v0);
+  state_store(a.um1, STATE, a.ndof, 3 * node + 1, v1);
+  state_store(a.um1, STATE, a.ndof, 3 * node + 2, v2);
+  return state_finite(STATE, v0) && state_finite(STATE, v1) && state_finite(STATE, v2);
+}
+
+// Central-difference update of the owned nodes written over u_{n-1} (or R_int, force-only),
+// node by node, with every operand loaded here (tiles that the block does not cover one node
+// per thread).  un_lds: u_n of the owned dofs as staged (FP64 staging holds u_n itself).
+template <bool FP32, int STATE>
 __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile& tile, const double* fl,
-                                            const double* un_lds, int force_only, int tid, int nt) {
-  const int64_t d0 = 3 * tile.own0;
-  const int n = 3 * tile.n_own;
+                                            const double* un_lds, int force_only, int64_t step, int tid, int nt) {
   if (force_only) {
+    const int64_t d0 = 3 * tile.own0;
     gmut_t<double> f = as_global_mut(a.f);
-    for (int i = tid; i < n; i += nt) f[d0 + i] = fl[i];
+    for (int i = tid; i < 3 * tile.n_own; i += nt) f[d0 + i] = fl[i];
     return;
   }
-  const double inv = 1.0 / (1.0 + a.c);
-  for (int i = tid; i < n; i += nt) {
-    const int64_t d = d0 + i;
-    const int32_t sm = state_of<RED>(a);
-    const double r = fl[i];
-    const double un = FP32 ? state_load(a.u, sm, a.ndof, d) : un_lds[i];
-    const double up = state_load(a.um1, sm, a.ndof, d);
-    const double v = (a.dt2 * minv_load(a.minv, sm, d) * (-r) + 2.0 * un - (1.0 - a.c) * up) * inv;
-    state_store(a.um1, sm, a.ndof, d, v);
+  bool ok = true;
+  for (int l = tid; l < tile.n_own; l += nt) {
+    const int64_t node = tile.own0 + l;
+    double m0, m1, m2;
+    minv_decode<STATE>(a, minv_raw<STATE>(a, node), m0, m1, m2);
+    double un[3], up[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      un[c] = FP32 ? state_load(a.u, STATE, a.ndof, 3 * node + c) : un_lds[3 * l + c];
+      up[c] = state_load(a.um1, STATE, a.ndof, 3 * node + c);
+    }
+    ok &= node_update<STATE>(a, node, fl + 3 * l, un[0], un[1], un[2], up[0], up[1], up[2], m0, m1, m2);
   }
+  if (!ok) atomicMin(a.flag, (unsigned long long)step);
 }
 
 // Stage u_n of the tile's local nodes in LDS (owned nodes first, then the tile's node list)
 // and clear the owned forces.  FP32 products keep u minus the displacement of the tile's
 // first owned node, so that only variations across the tile are rounded.
-template <bool FP32, bool RED>
+template <bool FP32, int STATE>
 __device__ __forceinline__ void tile_stage(const TiledArgs& a, const OwnerTile& tile, typename LdsType<FP32>::T* ul,
                                            double* fl, int tid, int nt) {
   gptr_t<int32_t> nodelist = as_global(a.nodelist);
   const int n_own = tile.n_own;
-  const int32_t sm = state_of<RED>(a);
+  constexpr int32_t sm = STATE;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
   if constexpr (FP32) {
     r0 = state_load(a.u, sm, a.ndof, 3 * tile.own0 + 0);
@@ -321,14 +405,24 @@ struct StagedNodes {
   double r[3], vo[3], v0[3], v1[3];
 };
 
-template <bool FP32, bool RED>
+// u_n at a block-uniform index through the constant space (scalar loads): u_n is read-only
+// during the pass (u_{n+1} goes to the other buffer)
+template <int STATE>
+__device__ __forceinline__ double state_load_uniform(const void* p, int64_t ndof, int64_t i) {
+  if constexpr (STATE == 0) return as_const((const double*)p)[i];
+  const cptr_t<float> q = as_const((const float*)p);
+  if constexpr (STATE == 1) return (double)q[i];
+  return (double)q[i] + (double)q[ndof + i];
+}
+
+template <bool FP32, int STATE>
 __device__ __forceinline__ StagedNodes stage_loads(const TiledArgs& a, int64_t own0, int n_own, int32_t h0,
                                                    int32_t h1, int tid) {
-  const int32_t sm = state_of<RED>(a);
+  constexpr int32_t sm = STATE;
   StagedNodes v{};
   if constexpr (FP32) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v.r[c] = state_load(a.u, sm, a.ndof, 3 * own0 + c);
+    for (int c = 0; c < 3; ++c) v.r[c] = state_load_uniform<STATE>(a.u, a.ndof, 3 * own0 + c);
   }
   if (tid < n_own) {
 #pragma unroll
@@ -420,7 +514,7 @@ __device__ __forceinline__ void hang_cell(const TiledArgs& a, const HangItem& it
       post = se / (double)su;
     }
   }
-  const gmut_t<double> res = as_global_mut(a.hres) + it.res0 + lane;
+  const gmut_t<T> res = as_global_mut((T*)a.hres) + it.res0 + lane;
 #pragma unroll
   for (int k = 0; k < NN; ++k) {
 #pragma unroll
@@ -430,7 +524,7 @@ __device__ __forceinline__ void hang_cell(const TiledArgs& a, const HangItem& it
 #pragma unroll
       for (int j = 0; j < ND; ++j) acc = fma(Kl[i * NDP + j], ue[j], acc);
       const double sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
-      res[(int64_t)i * 64] = sc * post * (double)acc;  // to node k, component pi(c)
+      res[(int64_t)i * 64] = (T)(sc * post * (double)acc);  // to node k, component pi(c)
     }
   }
 }
@@ -484,41 +578,47 @@ __global__ void __launch_bounds__(512, FP32 ? 4 : 1) tiled_hang(MeshRef single, 
 
 // One owner tile (steps 1-4 of the pass).  own0 and n_own come from the tile index and the
 // tile size, so that the loads that need nothing else (the update operands of the thread's
-// owned dofs, at most 3 per thread with FP64 state, and with `ids` the staging of the owned
-// nodes and of the halo nodes h0, h1) are issued while the tile record is still on its way;
-// the record feeds the item loop, the loads and the hanging-cell forces.
-template <bool FP32, bool RED>
+// owned node -- u_{n-1} and its inverse mass -- and, with `ids`, the staging of the owned node
+// and of the halo nodes h0, h1) are issued while the tile record is still on its way; the
+// record feeds the item loop, the loads and the hanging-cell forces.  With `ids` each thread
+// owns one node, whose staged u_n also serves the update.
+template <int PROD, int STATE>
 __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& tile, int64_t own0, int n_own,
                                            int64_t step, int force_only, bool ids, int32_t h0, int32_t h1,
                                            double* lds) {
+  constexpr bool FP32 = PROD != 0;
   using T = typename LdsType<FP32>::T;
+  using R = typename MinvRaw<STATE>::T;
   double* fl = lds;
-  T* ul = (T*)(lds + 3 * (int64_t)n_own);
+  // the staged u starts 16-byte aligned (FP32 staging reads float4 nodes)
+  T* ul = (T*)(lds + ((3 * (int64_t)n_own + 1) & ~(int64_t)1));
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int n_waves = nt >> 6;
+  // update operands of the thread's owned dofs tid, tid + nt, tid + 2 nt (consecutive dofs in
+  // consecutive lanes): u_{n-1}, the node's raw inverse mass and, for FP32 products, u_n
   constexpr int kPre = 3;
   const int n_dof = 3 * n_own;
-  const bool pre = !RED && !force_only && n_dof <= kPre * nt;
-  double pu[kPre], pp[kPre], pm[kPre];
+  const bool pre = !force_only && n_dof <= kPre * nt;  // uniform
+  double pu[kPre], pp[kPre];
+  R mr[kPre];
   if (pre) {
     const int64_t d0 = 3 * own0;
-    const gptr_t<double> u = as_global((const double*)a.u), up = as_global((const double*)a.um1),
-                         mi = as_global((const double*)a.minv);
 #pragma unroll
     for (int j = 0; j < kPre; ++j) {
       const int i = tid + j * nt;
-      pu[j] = pp[j] = pm[j] = 0.0;
+      pu[j] = pp[j] = 0.0;
+      mr[j] = 0;
       if (i < n_dof) {
-        if constexpr (FP32) pu[j] = u[d0 + i];
-        pp[j] = up[d0 + i];
-        pm[j] = mi[d0 + i];
+        if constexpr (FP32) pu[j] = state_load(a.u, STATE, a.ndof, d0 + i);
+        pp[j] = state_load(a.um1, STATE, a.ndof, d0 + i);
+        mr[j] = minv_raw<STATE>(a, own0 + i / 3);
       }
     }
   }
   StagedNodes sv{};
-  if (ids) sv = stage_loads<FP32, RED>(a, own0, n_own, h0, h1, tid);
+  if (ids) sv = stage_loads<FP32, STATE>(a, own0, n_own, h0, h1, tid);
   cptr_t<CellItem> items = as_const(a.items) + tile.item0;
   int w = wave;
   CellItem it{};
@@ -530,10 +630,10 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
   if (ids)
     stage_stores<FP32>(sv, n_own, h0, h1, ul, fl, tid, nt);
   else
-    tile_stage<FP32, RED>(a, tile, ul, fl, tid, nt);
+    tile_stage<FP32, STATE>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
-  tile_hang_forces(a, tile, fl, tid, nt);
+  tile_hang_forces<FP32>(a, tile, fl, tid, nt);
   while (w < tile.n_items) {
     // the next record is requested before this cell's work
     const int wn = w + n_waves;
@@ -543,7 +643,7 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
       itn = load_const(items + wn);
       if (lane < itn.count) qn = cell8_record(a, itn, lane);
     }
-    if (lane < it.count) cell8<FP32, RED>(a, it, q, n_own, ul, fl);
+    if (lane < it.count) cell8<FP32, round_mode<PROD>()>(a, it, q, n_own, ul, fl);
     w = wn;
     it = itn;
     q = qn;
@@ -551,26 +651,32 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
   __syncthreads();
   if (pre) {
     const int64_t d0 = 3 * own0;
-    const gmut_t<double> up = as_global_mut((double*)a.um1);
-    const double inv = 1.0 / (1.0 + a.c);
+    const double inv = 1.0 / (1.0 + a.c), cm = 1.0 - a.c;
+    bool ok = true;
 #pragma unroll
     for (int j = 0; j < kPre; ++j) {
       const int i = tid + j * nt;
       if (i < n_dof) {
-        const double r = fl[i];
+        const double m = minv_of_dof<STATE>(a, mr[j], i % 3);
         const double un = FP32 ? pu[j] : (double)ul[i];
-        up[d0 + i] = (a.dt2 * pm[j] * (-r) + 2.0 * un - (1.0 - a.c) * pp[j]) * inv;
+        const double v = (a.dt2 * m * (-fl[i]) + 2.0 * un - cm * pp[j]) * inv;
+        state_store(a.um1, STATE, a.ndof, d0 + i, v);
+        ok &= state_finite(STATE, v);
       }
     }
+    if (!ok) atomicMin(a.flag, (unsigned long long)step);
   } else {
-    tile_update<FP32, RED>(a, tile, fl, (const double*)ul, force_only, tid, nt);
+    tile_update<FP32, STATE>(a, tile, fl, (const double*)ul, force_only, step, tid, nt);
   }
 }
 
 // Owner-tile pass, one block per work unit (a tile; in a batched launch a (mesh, tile)).
 // With halo lists at a fixed stride and tiles that fit the block (owned nodes one per
 // thread, halo nodes two per thread), the halo ids are the block's first loads.
-template <bool FP32, bool RED>
+// PROD: sbfem_prod of the Walsh product (FP64; FP32; FP16 / BF16 operands with FP32
+// arithmetic); STATE: sbfem_state of u_n, u_{n-1} (and of the inverse mass: FP32 with FP32
+// state, else FP64).
+template <int PROD, int STATE>
 __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
                                                    const TileWork* __restrict__ work, int64_t first,
                                                    int64_t count, int64_t k, int force_only) {
@@ -591,7 +697,7 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
     if (tid + nt < H) h1 = nl[tid + nt];
   }
   const OwnerTile tile = load_const(as_const(a.tiles) + ti);
-  owner_tile<FP32, RED>(a, tile, own0, n_own, step, force_only, ids, h0, h1, lds);
+  owner_tile<PROD, STATE>(a, tile, own0, n_own, step, force_only, ids, h0, h1, lds);
 }
 
 }  // namespace sbfem

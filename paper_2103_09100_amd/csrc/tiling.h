@@ -37,7 +37,7 @@ struct TilingOutput {
   std::vector<uint16_t> lidx;
   std::vector<LoadEntry> loads;
   // scale classes of the pure 8-node tiles: key = level * 256 + material, in order of first use;
-  // an item of such a tile carries koff = 72 * class
+  // an item of such a tile carries koff = kWalshC * class
   std::vector<int32_t> scale_keys;
 };
 

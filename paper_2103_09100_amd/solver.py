@@ -37,12 +37,19 @@ class Simulation:
             dt = mesh.load.get("dt_factor", 0.5) * self.dt_cr
         desc.dt = float(dt)
         self.dt = float(dt)
-        self.footprint = binding.footprint(self.patterns, desc)
+        self._desc, self._keep, self._footprint = desc, keep, None
         self.gpu = binding.Mesh(self.patterns, desc, keep, stream)
         if graph_steps:
             self.gpu.set_graph_steps(graph_steps)
         self.stream = stream
         self.n_dof = mesh.n_dof
+
+    @property
+    def footprint(self):
+        """Device bytes of this mesh by the library's admission estimate (runs its host set-up)."""
+        if self._footprint is None:
+            self._footprint = binding.footprint(self.patterns, self._desc)
+        return self._footprint
 
     def step(self, n):
         self.gpu.step(n, self.stream)

@@ -287,7 +287,7 @@ def test_torch_caching_allocator_supplies_device_memory(sim_mod):
     finally:
         use_hip_allocator()
     _say(f"[torch allocator] {grown / 1e6:.1f} MB from torch, footprint {b.footprint / 1e6:.1f} MB")
-    assert grown >= 0.5 * b.footprint
+    assert grown >= b.footprint  # every buffer of the mesh came from torch (plus its rounding)
     assert torch.cuda.memory_allocated() == before
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 

@@ -222,3 +222,22 @@ def test_relative_error_metric():
     a = {1: np.array([1.0, -2.0]), 2: np.array([0.5, 4.0])}
     b = {1: np.array([1.0, -2.0 + 1e-3]), 2: np.array([0.5, 4.0])}
     assert np.isclose(relative_error(b, a), 1e-3 / 4.0)
+
+
+def test_local_sampled_step_matches_full_step():
+    """The cell-local one-step form (no global arrays) equals a full step at the sampled nodes,
+    including nodes of hanging-node cells, load nodes and fixed nodes."""
+    from oracle.solver import sampled_step_local
+    m = configs.cfg2(lcoarse=2, lfine=4, delta=0.1)
+    o = Oracle(m)
+    dt = 0.5 * o.critical_dt()
+    u, um1 = configs.random_state(m.n_dof, seed=4, fixed=m.fixed)
+    full, _ = o.step(u, um1, 23, dt, alpha=0.3)
+    rng = np.random.default_rng(5)
+    hang = m.conn[m.conn_ptr[np.flatnonzero(m.cell_slots)[:10]]]
+    fixed_nodes = np.flatnonzero(m.fixed.reshape(-1, 3).all(1))[:5]
+    nodes = np.unique(np.concatenate([rng.choice(m.n_nodes, 30, replace=False), hang,
+                                      m.load_dof[:5] // 3, fixed_nodes]))
+    part = sampled_step_local(m, u, um1, 23, dt, nodes, alpha=0.3, cache=o.cache)
+    assert np.abs(part - full.reshape(-1, 3)[nodes]).max() <= 1e-14 * np.abs(full).max()
+    assert np.abs(part[np.isin(nodes, fixed_nodes)]).max() == 0.0
