@@ -168,6 +168,25 @@ sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream);
 sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream);
 
 /*
+ * sbfem_step_batch for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same arguments, results
+ * and errors as sbfem_step_batch, except:
+ *  - the work lists of the batched launches (mesh refs, (mesh, tile) and (mesh, item) lists)
+ *    go into a static buffer of SBFEM_NOALLOC_SCRATCH_BYTES per device, which the library
+ *    holds until the process ends; nothing is allocated or freed (no hipMalloc, no graphs);
+ *  - a batch whose lists exceed the buffer (24 B per mesh and 16 B per owner tile and per
+ *    hanging-cell item of its largest group, 256-byte aligned parts) fails with SBFEM_EINVAL
+ *    before any step is taken;
+ *  - all meshes must live on one device.
+ * Every call on a device shares that device's buffer, and each segment rewrites it before
+ * use (nothing in it needs to start at zero); calls that overlap on one device (other
+ * threads or streams) race on it.  The call returns after its work has completed, like
+ * sbfem_step_batch.
+ */
+#define SBFEM_NOALLOC_SCRATCH_BYTES (8u << 20)
+sbfem_status sbfem_step_batch_noalloc(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream);
+
+/*
  * Step loops in HIP graphs (owner-tile assembly only; the time loop of Alg. 1
  * replayed from a captured graph instead of launched step by step).  With
  * steps > 0, step_n runs every whole chunk of `steps` steps as one replay of a

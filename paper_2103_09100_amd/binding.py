@@ -36,7 +36,7 @@ LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
 
 EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint",
            "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n", "sbfem_set_graph_steps",
-           "sbfem_step_batch", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
+           "sbfem_step_batch", "sbfem_step_batch_noalloc", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
            "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_set_allocator",
            "sbfem_last_error"]
 KERNEL_CLASSES = ("load", "element_8node", "element_larger", "update")
@@ -70,6 +70,7 @@ _lib.sbfem_destroy_mesh.argtypes = [_P]
 _lib.sbfem_destroy_mesh.restype = None
 _lib.sbfem_step_n.argtypes = [_P, C.c_int64, _P]
 _lib.sbfem_step_batch.argtypes = [_P, C.c_int32, _P, _P]
+_lib.sbfem_step_batch_noalloc.argtypes = [_P, C.c_int32, _P, _P]
 _lib.sbfem_set_graph_steps.argtypes = [_P, C.c_int32]
 _lib.sbfem_read_state.argtypes = [_P, C.c_int32, _P, C.POINTER(C.c_int64), _P]
 _lib.sbfem_write_state.argtypes = [_P, _P, _P, C.c_int64, _P]
@@ -267,6 +268,16 @@ def step_batch(meshes, steps, stream=None):
     arr = (_P * len(meshes))(*[m.handle for m in meshes])
     st = np.ascontiguousarray(steps, dtype=np.int64)
     _check(_lib.sbfem_step_batch(arr, len(meshes), st.ctypes.data, _stream(stream)))
+
+
+def step_batch_noalloc(meshes, steps, stream=None):
+    """sbfem_step_batch_noalloc: the batch's work lists in the library's static device buffer."""
+    arr = (_P * len(meshes))(*[m.handle for m in meshes])
+    st = np.ascontiguousarray(steps, dtype=np.int64)
+    _check(_lib.sbfem_step_batch_noalloc(arr, len(meshes), st.ctypes.data, _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 _ALLOCATOR_KEEP = []  # the C callbacks must outlive every object created with them

@@ -1514,8 +1514,25 @@ static BatchLists* cached_lists(const std::vector<sbfem_mesh*>& act, int32_t G, 
   return b;
 }
 
+// Bytes of the work lists of one batched segment over these meshes in a scratch buffer:
+// refs, then the owner-tile list, then the hanging-cell item list (each 256-byte aligned).
+static size_t scratch_list_bytes(const std::vector<sbfem_mesh*>& act, size_t* off8, size_t* offm) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  int64_t n8 = 0, nm = 0;
+  for (const auto* m : act) {
+    n8 += m->n_pure8 + m->n_mixed;
+    nm += m->n_hang;
+  }
+  const size_t o8 = up(act.size() * sizeof(sbfem::MeshRef));
+  const size_t om = o8 + up((size_t)n8 * sizeof(sbfem::TileWork));
+  if (off8) *off8 = o8;
+  if (offm) *offm = om;
+  return om + (size_t)nm * sizeof(sbfem::TileWork);
+}
+
+// scratch != null: the work lists go into that device buffer (no allocation, no graphs)
 static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::vector<int64_t>& steps,
-                                hipStream_t s) {
+                                hipStream_t s, char* scratch = nullptr) {
   const size_t n = g.size();
   int64_t most = 0;
   int32_t G = g[0]->graph_steps;
@@ -1523,6 +1540,8 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
     most = std::max(most, steps[i]);
     G = std::min(G, g[i]->graph_steps);
   }
+  if (scratch) G = 0;
+  std::vector<std::vector<sbfem::TileWork>> keep_work;  // host lists of the async copies
   sbfem::TiledLaunch L0 = tiled_launch(g[0], false);
   for (auto* m : g) {
     L0.lds = std::max(L0.lds, (size_t)m->lds_bytes);
@@ -1544,6 +1563,30 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
     BatchLists* b = nullptr;
     if (G > 0) {
       b = cached_lists(act, G, s, e);
+    } else if (scratch) {
+      // the lists of this segment written into the scratch buffer, behind the work of the
+      // previous segment on the same stream
+      b = new BatchLists();
+      b->meshes = act;
+      size_t o8 = 0, om = 0;
+      (void)scratch_list_bytes(act, &o8, &om);
+      keep_work.emplace_back();
+      keep_work.emplace_back();
+      auto& w8 = keep_work[keep_work.size() - 2];
+      auto& wm = keep_work.back();
+      for (size_t i = 0; i < act.size(); ++i) {
+        for (int64_t t = 0; t < act[i]->n_pure8 + act[i]->n_mixed; ++t) w8.push_back({(int32_t)i, 0, t});
+        for (int64_t t = 0; t < act[i]->n_hang; ++t) wm.push_back({(int32_t)i, 0, t});
+      }
+      b->d_refs = (sbfem::MeshRef*)scratch;
+      b->d_w8 = (sbfem::TileWork*)(scratch + o8);
+      b->d_wm = (sbfem::TileWork*)(scratch + om);
+      b->n8 = (int64_t)w8.size();
+      b->nm = (int64_t)wm.size();
+      if (!w8.empty())
+        e = hipMemcpyAsync(b->d_w8, w8.data(), w8.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess && !wm.empty())
+        e = hipMemcpyAsync(b->d_wm, wm.data(), wm.size() * sizeof(sbfem::TileWork), hipMemcpyHostToDevice, s);
     } else {
       b = new BatchLists();
       b->meshes = act;
@@ -1572,7 +1615,9 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
       L.k = j - ref_k;
       e = sbfem::launch_tiled(L, s);
     }
-    if (G == 0 && b) {
+    if (scratch && b) {
+      delete b;  // points into the scratch buffer; nothing to free
+    } else if (G == 0 && b) {
       const hipError_t q = hipStreamSynchronize(s);  // the lists are in use until here
       if (e == hipSuccess) e = q;
       free_lists(b);
@@ -1591,7 +1636,10 @@ static sbfem_status batch_tiled(const std::vector<sbfem_mesh*>& g, const std::ve
   return SBFEM_OK;
 }
 
-sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream) {
+// Batched stepping (sbfem_step_batch); scratch != null: the work lists of the owner-tile groups
+// go into that device buffer of scratch_bytes (checked up front), with no allocation and no graphs.
+static sbfem_status step_batch_impl(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream,
+                                    char* scratch, size_t scratch_bytes) {
   if (n < 0 || (n > 0 && (!ms || !n_steps))) return fail(SBFEM_EINVAL, "bad batch arguments");
   hipStream_t s = (hipStream_t)hip_stream;
   for (int i = 0; i < n; ++i) {
@@ -1602,6 +1650,8 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
     if (st != SBFEM_OK) return st;
   }
   // groups of owner-tile meshes with one library and one precision
+  std::vector<std::vector<sbfem_mesh*>> groups;
+  std::vector<std::vector<int64_t>> group_steps;
   std::vector<char> used(n, 0);
   for (int i = 0; i < n; ++i) {
     if (used[i] || ms[i]->assembly != SBFEM_ASM_TILED || ms[i]->profiling) continue;
@@ -1618,10 +1668,23 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
         used[j] = 1;
       }
     if (!g.empty()) {
-      HIP_TRY(hipSetDevice(g[0]->device));
-      sbfem_status r = batch_tiled(g, st, s);
-      if (r != SBFEM_OK) return r;
+      groups.push_back(g);
+      group_steps.push_back(st);
     }
+  }
+  if (scratch) {
+    // every mesh of a group is active in its first segment: the largest lists
+    for (const auto& g : groups) {
+      const size_t need = scratch_list_bytes(g, nullptr, nullptr);
+      if (need > scratch_bytes)
+        return fail(SBFEM_EINVAL, "the batch needs %zu bytes of work lists, more than the %zu-byte scratch buffer",
+                    need, scratch_bytes);
+    }
+  }
+  for (size_t i = 0; i < groups.size(); ++i) {
+    HIP_TRY(hipSetDevice(groups[i][0]->device));
+    sbfem_status r = batch_tiled(groups[i], group_steps[i], s, scratch);
+    if (r != SBFEM_OK) return r;
   }
   // the rest, interleaved step by step
   int64_t most = 0;
@@ -1639,6 +1702,48 @@ sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n
       if (st != SBFEM_OK) return st;
     }
   return SBFEM_OK;
+}
+
+sbfem_status sbfem_step_batch(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream) {
+  return step_batch_impl(ms, n, n_steps, hip_stream, nullptr, 0);
+}
+
+}  // extern "C"
+
+// Per-device work-list buffer of sbfem_step_batch_noalloc.  In host code `scratch` names a
+// host-side stand-in: its device address comes from hipGetSymbolAddress, taken once per device.
+static __device__ __align__(256) char scratch[SBFEM_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_ptr;
+
+extern "C" {
+
+static sbfem_status scratch_of_device(int dev, char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    HIP_TRY(hipSetDevice(dev));
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    it = g_scratch_ptr.emplace(dev, (char*)ptr).first;
+  }
+  *out = it->second;
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_step_batch_noalloc(sbfem_mesh* const* ms, int32_t n, const int64_t* n_steps, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!ms || !n_steps))) return fail(SBFEM_EINVAL, "bad batch arguments");
+  int dev = -1;
+  for (int i = 0; i < n; ++i) {
+    if (!ms[i]) return fail(SBFEM_EINVAL, "bad batch entry %d", i);
+    if (dev < 0) dev = ms[i]->device;
+    if (ms[i]->device != dev) return fail(SBFEM_EINVAL, "the meshes of a batch must share one device");
+  }
+  if (n == 0) return SBFEM_OK;
+  char* ptr = nullptr;
+  sbfem_status st = scratch_of_device(dev, &ptr);
+  if (st != SBFEM_OK) return st;
+  return step_batch_impl(ms, n, n_steps, hip_stream, ptr, SBFEM_NOALLOC_SCRATCH_BYTES);
 }
 
 sbfem_status sbfem_read_state(sbfem_mesh* m, int32_t which, double* host_out, int64_t* step, void* hip_stream) {
