@@ -265,9 +265,10 @@ def _ellipsoid_radius(x, ells, chunk=1 << 22):
     return out
 
 
-def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=1.05, keep_node_lat=True, nu=0.25, n_incl=3):
+def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=1.05, keep_node_lat=True, nu=0.25, n_incl=3, nu_incl=None):
     """Ellipsoid-inclusion octree (cfg3 recipe): level lfine where the scaled
-    ellipsoid radius is below 1+band, level lcoarse elsewhere; E=5, rho=2 inside."""
+    ellipsoid radius is below 1+band, level lcoarse elsewhere; E=5, rho=2 inside, and the
+    Poisson ratio nu_incl inside when given (a second pattern library)."""
     ells = ellipsoids(seed, n_incl)
 
     def refine(level, idx):
@@ -280,7 +281,7 @@ def inclusion_mesh(seed=0, lcoarse=8, lfine=9, band=1.05, keep_node_lat=True, nu
 
     m = build_mesh((1, 1, 1), 1.0, lcoarse, lfine, refine, material=material,
                    mat_E=(1.0, 5.0), mat_rho=(1.0, 2.0), nu=nu, fixed=_base_fixed,
-                   keep_node_lat=True)
+                   keep_node_lat=True, mat_nu=None if nu_incl is None else (nu, nu_incl))
     rng = np.random.default_rng([33, seed])
     face = [(0, 0), (0, 1), (1, 0), (1, 1), (2, 1)][int(rng.integers(0, 5))]
     pc = rng.uniform(0.1, 0.9, size=2)

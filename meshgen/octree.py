@@ -72,6 +72,13 @@ class Mesh:
     load_val: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float64))
     load: dict = field(default_factory=dict)   # time function parameters
     meta: dict = field(default_factory=dict)
+    mat_nu: np.ndarray = None       # float64 [n_mat] Poisson ratio per material (None: nu for all)
+
+    def material_nu(self):
+        """Poisson ratio of every material (the mesh-wide nu unless given per material)."""
+        if self.mat_nu is None:
+            return np.full(len(self.mat_E), self.nu)
+        return np.asarray(self.mat_nu, dtype=np.float64)
 
     @property
     def n_cells(self):
@@ -100,6 +107,8 @@ class Mesh:
                   self.mat_rho, self.fixed, self.load_dof, self.load_val):
             h.update(np.ascontiguousarray(a).tobytes())
         h.update(repr((self.roots, self.h0, self.lmax, self.n_nodes, self.nu)).encode())
+        if self.mat_nu is not None:  # per-material ratios (the mesh-wide nu is hashed above)
+            h.update(self.material_nu().tobytes())
         return h.hexdigest()
 
 
@@ -185,7 +194,7 @@ def build_native():
 
 
 def build_mesh(roots, h0, lmin, lmax, refine, material=None, mat_E=(1.0,), mat_rho=(1.0,),
-               nu=0.25, fixed=None, keep_node_lat=True):
+               nu=0.25, fixed=None, keep_node_lat=True, mat_nu=None):
     """Build a balanced octree mesh.
 
     material(xyz_centres (k,3)) -> uint8 material id per cell (default all 0).
@@ -228,7 +237,8 @@ def build_mesh(roots, h0, lmin, lmax, refine, material=None, mat_E=(1.0,), mat_r
              cell_level=cell_level, cell_lat=cell_lat, cell_slots=cell_slots,
              conn_ptr=conn_ptr, conn=conn, node_lat=node_lat, cell_mat=cell_mat,
              mat_E=np.asarray(mat_E, dtype=np.float64),
-             mat_rho=np.asarray(mat_rho, dtype=np.float64), nu=float(nu), fixed=fx)
+             mat_rho=np.asarray(mat_rho, dtype=np.float64), nu=float(nu), fixed=fx,
+             mat_nu=None if mat_nu is None else np.asarray(mat_nu, dtype=np.float64))
     return m
 
 

@@ -3,7 +3,8 @@
 Set-up (Alg. 1, initialisation part):
   * each cell layout (slot mask) gets its own SBFEM matrices from
     :class:`oracle.element.Cell` at unit size, modulus and density, computed
-    in the cell's natural node order;
+    in the cell's natural node order, for the Poisson ratio of the cell's material
+    (E and rho scale the unit matrices, nu does not: Sec. 3.2.3);
   * cell matrices scale as K = E h K_unit and M = rho h^3 M_unit (eq. KM_scale);
   * the global diagonal mass is the sum of the cells' lumped masses;
     Dirichlet dofs are enforced by a zero inverse mass (the dof never moves);
@@ -29,31 +30,41 @@ def _make_cell(args):
 
 
 class Oracle:
+    """Cell matrices are cached per (slot mask, Poisson ratio); ``groups`` lists, per such
+    key, the cells and their dofs."""
+
     def __init__(self, mesh, cell_cache=None, workers=0):
         self.mesh = mesh
         self.cache = {} if cell_cache is None else cell_cache
-        self._prefill(np.unique(mesh.cell_slots.astype(np.int64)), workers)
+        mat_nu = mesh.material_nu()
+        self.nus = np.unique(mat_nu)
+        # layout key of every cell: slot mask and the index of its material's Poisson ratio
+        nu_idx = np.searchsorted(self.nus, mat_nu)[np.asarray(mesh.cell_mat, dtype=np.int64)]
+        keys = mesh.cell_slots.astype(np.int64) * len(self.nus) + nu_idx
+        self._key_nu = lambda k: (int(k) // len(self.nus), float(self.nus[int(k) % len(self.nus)]))
+        self._cell_keys = keys
+        self._prefill([self._key_nu(k) for k in np.unique(keys)], workers)
         n_dof = mesh.n_dof
         self.n_dof = n_dof
-        masks = mesh.cell_slots.astype(np.int64)
         self.groups = []
         h = mesh.cell_h()
         E = mesh.mat_E[mesh.cell_mat]
         rho = mesh.mat_rho[mesh.cell_mat]
         self.k_scale = E * h
         self.m_scale = rho * h ** 3
-        for mask in np.unique(masks):
-            cells = np.flatnonzero(masks == mask)
-            cell = self.cell(int(mask))
+        for key in np.unique(keys):
+            cells = np.flatnonzero(keys == key)
+            ck = self._key_nu(key)
+            cell = self.cell(*ck)
             n = cell.n_nodes
             nodes = mesh.conn[mesh.conn_ptr[cells][:, None] + np.arange(n)[None, :]].astype(np.int64)
             dofs = (3 * nodes[:, :, None] + np.arange(3)[None, None, :]).reshape(len(cells), 3 * n)
-            self.groups.append((int(mask), cells, dofs))
+            self.groups.append((ck, cells, dofs))
         self._all_dofs = np.concatenate([g[2].ravel() for g in self.groups])
         # lumped global mass
         mdiag = np.zeros(n_dof)
-        for mask, cells, dofs in self.groups:
-            m = self.cache[mask].m
+        for key, cells, dofs in self.groups:
+            m = self.cache[key].m
             mdiag += np.bincount(dofs.ravel(), (self.m_scale[cells][:, None] * m[None, :]).ravel(),
                                  minlength=n_dof)
         self.mdiag = mdiag
@@ -64,23 +75,27 @@ class Oracle:
         self.b = np.zeros(n_dof)
         np.add.at(self.b, mesh.load_dof, mesh.load_val)
 
-    def _prefill(self, masks, workers):
-        """Compute missing cell layouts, optionally in a process pool."""
-        todo = [int(m) for m in masks if int(m) not in self.cache]
+    def _prefill(self, keys, workers):
+        """Compute missing (mask, nu) cell layouts, optionally in a process pool."""
+        todo = [k for k in keys if k not in self.cache]
         if workers and len(todo) > 8:
             from concurrent.futures import ProcessPoolExecutor
             import multiprocessing as mp
             with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
-                for m, c in zip(todo, ex.map(_make_cell, [(m, self.mesh.nu) for m in todo],
-                                             chunksize=4)):
-                    self.cache[m] = c
-        for m in todo:
-            self.cell(m)
+                for k, c in zip(todo, ex.map(_make_cell, todo, chunksize=4)):
+                    self.cache[k] = c
+        for k in todo:
+            self.cell(*k)
 
-    def cell(self, mask):
-        if mask not in self.cache:
-            self.cache[mask] = Cell(mask, self.mesh.nu)
-        return self.cache[mask]
+    def cell(self, mask, nu):
+        key = (int(mask), float(nu))
+        if key not in self.cache:
+            self.cache[key] = Cell(int(mask), float(nu))
+        return self.cache[key]
+
+    def cell_of(self, c):
+        """The matrices of cell c (its layout and its material's Poisson ratio)."""
+        return self.cell(*self._key_nu(self._cell_keys[c]))
 
     def critical_dt(self):
         """min over cells of 2/omega_max,e with omega_max,e = omega_unit sqrt(E/rho)/h."""
@@ -89,8 +104,8 @@ class Oracle:
         E = mesh.mat_E[mesh.cell_mat]
         rho = mesh.mat_rho[mesh.cell_mat]
         best = np.inf
-        for mask, cells, _ in self.groups:
-            w = self.cache[mask].omega_max * np.sqrt(E[cells] / rho[cells]) / h[cells]
+        for key, cells, _ in self.groups:
+            w = self.cache[key].omega_max * np.sqrt(E[cells] / rho[cells]) / h[cells]
             best = min(best, float((2.0 / w).min()))
         return best
 
@@ -98,8 +113,8 @@ class Oracle:
         """R_int = sum_e (E h)_e K_unit U_e: one product per layout, then one
         scatter of every element force in a fixed order (layouts ascending)."""
         parts = []
-        for mask, cells, dofs in self.groups:
-            K = self.cache[mask].K
+        for key, cells, dofs in self.groups:
+            K = self.cache[key].K
             U = u[dofs]
             parts.append(((U @ K.T) * self.k_scale[cells][:, None]).ravel())
         return np.bincount(self._all_dofs, np.concatenate(parts), minlength=self.n_dof)
@@ -108,8 +123,8 @@ class Oracle:
         """Assembled global K (scipy CSR) for checks."""
         from scipy import sparse
         rows, cols, vals = [], [], []
-        for mask, cells, dofs in self.groups:
-            K = self.cache[mask].K
+        for key, cells, dofs in self.groups:
+            K = self.cache[key].K
             n = K.shape[0]
             rows.append(np.repeat(dofs, n, axis=1).ravel())
             cols.append(np.tile(dofs, (1, n)).ravel())
@@ -138,8 +153,13 @@ class Oracle:
         unew = (dt * dt * self.minv * r + 2.0 * u - (1.0 - c) * um1) / (1.0 + c)
         return unew, f
 
-    def run(self, n_steps=None, dt=None, snap_every=50, energy=True, u0=None, v0=None, state=None):
-        """Run Alg. 1; returns dict with dt, snapshots {n: u_n}, energy terms, final state."""
+    def run(self, n_steps=None, dt=None, snap_every=50, energy=True, u0=None, v0=None, state=None, probes=None):
+        """Run Alg. 1; returns dict with dt, snapshots {n: u_n}, energy terms, final state.
+
+        probes: dofs whose time histories are kept (displacement at a point, Sec. 5.2;
+        acceleration, Sec. 5.3): row k of probe_u holds u_{n+1} of step n = n0 + k, row k of
+        probe_a the central-difference acceleration (u_{n+1} - 2 u_n + u_{n-1}) / dt^2 at t_n.
+        """
         load = self.mesh.load
         if n_steps is None:
             n_steps = load["n_steps"]
@@ -154,6 +174,8 @@ class Oracle:
             n0 = 0
         snaps = {}
         H, W = [], []
+        probes = None if probes is None else np.asarray(probes, dtype=np.int64)
+        pu, pa = [], []
         if energy:
             d = u - um1
             H.append(0.5 * (d @ (self.mdiag * d)) / dt ** 2 + 0.5 * (u @ self.internal_force(um1)))
@@ -165,12 +187,18 @@ class Oracle:
                 d = unew - u
                 H.append(0.5 * (d @ (self.mdiag * d)) / dt ** 2 + 0.5 * (unew @ f))
                 W.append(W[-1] + 0.5 * ((unew - um1) @ (self.load_at(n * dt) * self.b)))
+            if probes is not None:
+                pu.append(unew[probes])
+                pa.append((unew[probes] - 2.0 * u[probes] + um1[probes]) / (dt * dt))
             um1, u = u, unew
             m = n + 1
             if (snap_every and m % snap_every == 0) or k == n_steps - 1:
                 snaps[m] = u.copy()
-        return dict(dt=dt, snapshots=snaps, H=np.array(H), W=np.array(W), u=u, um1=um1,
-                    step=n0 + n_steps)
+        out = dict(dt=dt, snapshots=snaps, H=np.array(H), W=np.array(W), u=u, um1=um1, step=n0 + n_steps)
+        if probes is not None:
+            out["probe_u"] = np.array(pu).reshape(n_steps, len(probes))
+            out["probe_a"] = np.array(pa).reshape(n_steps, len(probes))
+        return out
 
     def sampled_step(self, u, um1, n, dt, nodes, alpha=0.0):
         """u_{n+1} at the given nodes only: each incident cell's force at that node."""
@@ -183,7 +211,7 @@ class Oracle:
             nd = int(mesh.conn[p])
             lo, hi = mesh.conn_ptr[c], mesh.conn_ptr[c + 1]
             cn = mesh.conn[lo:hi].astype(np.int64)
-            K = self.cache[int(mesh.cell_slots[c])].K
+            K = self.cell_of(c).K
             i = int(p - lo)
             ue = u[(3 * cn[:, None] + np.arange(3)).ravel()]
             f[nd] += self.k_scale[c] * (K[3 * i:3 * i + 3] @ ue)
@@ -214,11 +242,12 @@ def sampled_step_local(mesh, u, um1, n, dt, nodes, alpha=0.0, cache=None):
     rho = mesh.mat_rho[mesh.cell_mat[cells]]
     f = {int(v): np.zeros(3) for v in nodes}
     mass = {int(v): np.zeros(3) for v in nodes}
+    mat_nu = mesh.material_nu()
     for p, c, hc, Ec, rc in zip(pos, cells, h, E, rho):
-        mask = int(mesh.cell_slots[c])
-        if mask not in cache:
-            cache[mask] = Cell(mask, mesh.nu)
-        cell = cache[mask]
+        key = (int(mesh.cell_slots[c]), float(mat_nu[mesh.cell_mat[c]]))
+        if key not in cache:
+            cache[key] = Cell(*key)
+        cell = cache[key]
         lo, hi = mesh.conn_ptr[c], mesh.conn_ptr[c + 1]
         cn = mesh.conn[lo:hi].astype(np.int64)
         i = int(p - lo)

@@ -64,7 +64,7 @@ def test_ebe_force_equals_assembled_and_bruteforce():
     for c in range(m.n_cells):
         nodes = m.cell_nodes(c).astype(np.int64)
         dofs = (3 * nodes[:, None] + np.arange(3)).ravel()
-        g[dofs] += o.k_scale[c] * (o.cache[int(m.cell_slots[c])].K @ u[dofs])
+        g[dofs] += o.k_scale[c] * (o.cell_of(c).K @ u[dofs])
     assert np.abs(f - g).max() < 1e-12 * np.abs(f).max()
     # assembled K symmetric, rigid modes removed only by the fixed base
     assert abs(K - K.T).max() < 1e-12 * abs(K).max()
@@ -241,3 +241,66 @@ def test_local_sampled_step_matches_full_step():
     part = sampled_step_local(m, u, um1, 23, dt, nodes, alpha=0.3, cache=o.cache)
     assert np.abs(part - full.reshape(-1, 3)[nodes]).max() <= 1e-14 * np.abs(full).max()
     assert np.abs(part[np.isin(nodes, fixed_nodes)]).max() == 0.0
+
+
+def _chain_k(ks, dt, n_steps, P):
+    """1D lumped linear-element chain (A = rho = h = 1), element stiffnesses ks, fixed at node 0,
+    force P(t) at the free end."""
+    n_el = len(ks)
+    k = np.zeros((n_el + 1, n_el + 1))
+    for e, ke in enumerate(ks):
+        k[e:e + 2, e:e + 2] += ke * np.array([[1, -1], [-1, 1.0]])
+    mass = np.ones(n_el + 1)
+    mass[-1] = 0.5
+    minv = 1 / mass
+    minv[0] = 0.0
+    b = np.zeros(n_el + 1)
+    b[-1] = 1.0
+    u = np.zeros(n_el + 1)
+    um1 = 0.5 * dt * dt * minv * P(0.0) * b
+    hist = []
+    for n in range(n_steps):
+        unew = dt * dt * minv * (P(n * dt) * b - k @ u) + 2 * u - um1
+        um1, u = u, unew
+        hist.append(u.copy())
+    return np.array(hist)
+
+
+def _two_nu_bar(nx, nus):
+    """nx x 1 x 1 unit cells, fixed at x = 0, every lateral dof held (uniaxial strain), material 1
+    (Poisson ratio nus[1]) in x > nx/2, uniform end pressure; E = rho = 1."""
+    from meshgen.octree import build_mesh
+
+    def fixed(lat, lmax):
+        out = np.ones(lat.shape, dtype=bool)
+        out[:, 0] = lat[:, 0] == 0
+        return out
+    m = build_mesh((nx, 1, 1), 1.0, 0, 0, lambda l, i: np.zeros(len(i), bool),
+                   material=lambda xyz: (xyz[:, 0] > nx / 2).astype(np.uint8), mat_E=(1.0, 1.0),
+                   mat_rho=(1.0, 1.0), nu=nus[0], fixed=fixed, mat_nu=nus)
+    configs.patch_load(m, (0, 1), (0.5, 0.5), 1.0, pressure=-1.0)
+    return m
+
+
+def test_two_poisson_ratios_reduce_to_chain():
+    """Each material uses its own Poisson ratio (its own pattern library, Sec. 3.2.3): with every
+    lateral dof held, the bar is exactly the 1D lumped chain whose element stiffness is the
+    constrained modulus E (1 - nu) / ((1 + nu)(1 - 2 nu)) of the element's material."""
+    nx, nus, t1 = 24, (0.2, 0.35), 12.0
+    m = _two_nu_bar(nx, nus)
+    m.load = dict(kind="ricker", t1=t1, P0=1.0, dt_factor=0.5, n_steps=0, alpha=0.0)
+    o = Oracle(m)
+    dt = 0.5 * o.critical_dt()
+    n_steps = 300
+    snaps = o.run(n_steps=n_steps, dt=dt, snap_every=1, energy=False)["snapshots"]
+    mc = lambda nu: (1 - nu) / ((1 + nu) * (1 - 2 * nu))
+    ks = [mc(nus[1] if e + 0.5 > nx / 2 else nus[0]) for e in range(nx)]
+    chain = _chain_k(ks, dt, n_steps, lambda t: loads.ricker(t, t1))
+    sec = m.node_lat[:, 0].astype(np.int64)
+    scale = np.abs(chain).max()
+    for n in range(1, n_steps + 1, 9):
+        u = snaps[n].reshape(-1, 3)
+        assert np.abs(u[:, 0] - chain[n - 1][sec]).max() < 1e-11 * scale
+    # the same bar read with one Poisson ratio for both halves is a different chain
+    one = _chain_k([mc(nus[0])] * nx, dt, n_steps, lambda t: loads.ricker(t, t1))
+    assert np.abs(one - chain).max() > 1e-3 * scale

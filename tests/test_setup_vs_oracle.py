@@ -58,7 +58,7 @@ def test_linked_cells_reproduce_direct_cells(lib, seed):
         nat = mesh.conn[lo:hi].astype(np.int64)
         mst = conn[lo:hi].astype(np.int64)
         assert sorted(nat.tolist()) == sorted(mst.tolist())
-        K_or = o.cache[int(mesh.cell_slots[c])].K
+        K_or = o.cell_of(c).K
         Q = pt.ORIENT_Q[code[c]]
         n = len(nat)
         # R maps cell dofs (natural order) to master dofs: u_master[k] = Q u[mst[k]]
@@ -70,4 +70,4 @@ def test_linked_cells_reproduce_direct_cells(lib, seed):
         K_gpu = R.T @ lib.K[pid[c]] @ R
         assert np.abs(K_gpu - K_or).max() <= 1e-11 * np.abs(K_or).max(), c
         m_gpu = np.abs(R.T) @ lib.m[pid[c]]
-        assert np.allclose(m_gpu, o.cache[int(mesh.cell_slots[c])].m, rtol=1e-11)
+        assert np.allclose(m_gpu, o.cell_of(c).m, rtol=1e-11)
