@@ -45,10 +45,10 @@ def log(*a):
 
 
 def algorithmic_bytes(mesh):
-    """Bytes per step under the per-dof model (FP64 state, FP64 inverse mass per dof): per dof
-    u_n, u_{n-1}, M^-1 read and u_{n+1} written (8 B each); per cell its node ids (4 B each)
-    and orientation, level, material (1 B each); per load entry index + value (16 B).  The
-    library reports the bytes of its own storage (inverse mass per node) per pass."""
+    """Bytes the method must move per step (FP64 state): per dof u_n, u_{n-1}, M^-1 read and
+    u_{n+1} written (8 B each); per cell its node ids (4 B each) and orientation, level,
+    material (1 B each); per load entry index + value (16 B).  The library reports the same
+    count per pass, for the mesh's state storage."""
     return 32 * mesh.n_dof + 4 * int(mesh.conn.shape[0]) + 3 * mesh.n_cells + 16 * len(mesh.load_dof)
 
 
@@ -319,6 +319,30 @@ def serving(torch, args):
     return out
 
 
+def oracle_snapshots(mesh, steps, every):
+    """The FP64 oracle's stored snapshots of this mesh (tests/golden), or None when the file
+    does not cover this run (another mesh, step count or snapshot spacing)."""
+    path = os.path.join(ROOT, "tests", "golden", "cfg4_oracle_snapshots.txt")
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.dirname(path))
+    from make_oracle_snapshots import read
+    ref = read(path)
+    if ref["mesh_fingerprint"] != mesh.fingerprint() or ref["steps"] != steps or ref["every"] != every:
+        return None
+    return ref
+
+
+def golden_error(ref, snaps):
+    """e_max over the stored sample nodes and max nodes, over the largest stored |u|_inf."""
+    sample = ref["sample_nodes"]
+    num = 0.0
+    for r in ref["snaps"]:
+        u = snaps[r["step"]].reshape(-1, 3)
+        num = max(num, float(np.abs(u[sample] - r["u"]).max()), float(np.abs(u[r["imax"]] - r["umax"]).max()))
+    return num / max(r["norm"] for r in ref["snaps"])
+
+
 def precision_sweep(torch, args):
     """Products FP64/FP32/FP16/BF16 x state FP64/compensated FP32/FP32 on the cfg4 mesh.
     Per combination: DOF-steps/s over a timed run; the max relative displacement error over
@@ -349,6 +373,7 @@ def precision_sweep(torch, args):
         d = u - un
         return 0.5 * (d @ (M * d)) / dt ** 2 + 0.5 * (u @ f)
 
+    golden = oracle_snapshots(mesh, n_total, every)
     ref_snaps, rows = {}, []
     combos = [(p, st) for p in ("fp64", "fp32", "fp16", "bf16") for st in ("fp64", "kahan32", "fp32")]
     for prod, state in combos:
@@ -375,9 +400,12 @@ def precision_sweep(torch, args):
         drift = float(np.abs(H - H[0]).max() / abs(H[0])) if len(H) > 1 else float("nan")
         row = dict(product=prod, state=state, ms_per_step=ms, dof_steps_per_s=mesh.n_dof / (ms * 1e-3),
                    e_max_vs_fp64=num / den, energy_drift=drift, energy_samples=len(H))
+        if golden is not None:
+            row["e_max_vs_oracle_sampled"] = golden_error(golden, snaps)
         rows.append(row)
         log(f"[sweep] {prod} products, {state} state: {ms:.3f} ms/step ({row['dof_steps_per_s']:.3e} DOF-steps/s), "
-            f"e_max vs FP64 {row['e_max_vs_fp64']:.3e}, energy drift {drift:.3e} ({len(H)} samples)")
+            f"e_max vs FP64 {row['e_max_vs_fp64']:.3e}, vs oracle (sampled) "
+            f"{row.get('e_max_vs_oracle_sampled', float('nan')):.3e}, energy drift {drift:.3e} ({len(H)} samples)")
     evaluator.close()
     return dict(workload=f"cfg4 sphere-band octree L4/8, {mesh.n_dof} dofs, {mesh.n_cells} cells",
                 steps=n_total, snapshot_every=every, load_ends_at_step=t_end, energy_steps=h_at, rows=rows)
@@ -625,9 +653,8 @@ def main():
     fp64 = next((m for m in args.modes.split(",") if m.startswith("fp64:")), None)
     r = results[head]
     roof = roofline_block(r, copy_gbs, head.split(":")[0])
-    # the same time against the per-dof byte model (FP64 inverse mass per dof)
-    roof["alg_bytes_per_step_per_dof_model"] = ab["step"]
-    roof["step_frac_per_dof_model"] = ab["step"] / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if roof["alg_bytes_per_step"] != ab["step"]:
+        log(f"[bench] warning: per-pass algorithmic bytes {roof['alg_bytes_per_step']} != step bytes {ab['step']}")
     out = {
         "metric": METRIC,
         "value": r["value"],

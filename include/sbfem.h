@@ -36,7 +36,8 @@ typedef enum {
   SBFEM_ENOMEM = -2,     /* device allocation failed or over the memory budget */
   SBFEM_EDEVICE = -3,    /* a HIP runtime call failed */
   SBFEM_EUNSTABLE = -4,  /* non-finite displacement detected (time step too large) */
-  SBFEM_EBUSY = -5
+  SBFEM_EBUSY = -5,
+  SBFEM_ENOTCONV = -6    /* an iterative solve did not reach its tolerance */
 } sbfem_status;
 
 /* Precision of the element product K_p u_e.  FP32/FP16/BF16 accumulate in FP32. */
@@ -217,6 +218,47 @@ sbfem_status sbfem_write_state(sbfem_mesh* m, const double* u_n, const double* u
 
 /* Device bytes held by a mesh, and the number of cells per pattern-size class (diagnostics). */
 sbfem_status sbfem_mesh_info(const sbfem_mesh* m, int64_t* device_bytes, int64_t* n_dof, int32_t* n_colours);
+
+/*
+ * Probe time histories (displacement at a point, Sec. 5.2; acceleration history, Sec. 5.3):
+ * from the mesh's current step on, the update of every step n records, for each of the
+ * n_probes dofs (host, caller numbering), u_{n+1} and the central-difference acceleration
+ * (u_{n+1} - 2 u_n + u_{n-1}) / dt^2 into row n - n_0 of a device history of `capacity` rows
+ * (n_0: the step at this call); later steps are not recorded.  A dof may appear more than once.
+ * n_probes = 0 removes the probes.  Device memory: 16 B per probe and row, allocated here (not
+ * part of sbfem_mesh_footprint).  Owner-tile assembly only.  Waits for the stream's work.
+ * Errors: SBFEM_EINVAL (bad dof, negative count or capacity, other assembly), SBFEM_ENOMEM.
+ */
+sbfem_status sbfem_set_probes(sbfem_mesh* m, int32_t n_probes, const int64_t* dofs, int64_t capacity,
+                              void* hip_stream);
+
+/*
+ * The recorded rows: *rows = min(capacity, steps taken since sbfem_set_probes), *step0 = n_0;
+ * host_u and host_a [rows][n_probes] (row-major; either may be NULL, both NULL to query the
+ * count).  Blocks until the copies have landed.
+ */
+sbfem_status sbfem_read_probes(sbfem_mesh* m, double* host_u, double* host_a, int64_t* rows, int64_t* step0,
+                               void* hip_stream);
+
+/*
+ * Lowest eigenfrequencies of the free vibration K phi = omega^2 M phi with the lumped mass
+ * (Sec. 5.1): the k smallest omega over the free dofs, ascending, into host_omega [k], and the
+ * relative residuals |A x - theta x| / theta of the Ritz pairs into host_resid [k] (may be NULL),
+ * where A = M^-1/2 K M^-1/2 and theta = omega^2.  Chebyshev-filtered subspace iteration with
+ * a block of `block` vectors (0: k + max(16, k/2)) and filters of degree `degree` (0: 20)
+ * damping [largest Ritz value, max over cells of omega_max,e^2]; K is applied element by
+ * element by the owner-tile pass to the whole block in one launch; Rayleigh-Ritz with the
+ * block's Gram matrix every iteration.  Stops when every wanted residual is <= tol, or after
+ * max_iter iterations (*iterations receives the count; may be NULL).  The eigenvalues of
+ * A must be positive (Dirichlet conditions that remove the rigid modes).  Needs the owner-tile
+ * assembly with FP64 products and state.  Device memory: 6 blocks of 3N x block FP64 values
+ * plus the hanging-cell rows of every column, allocated for the call and freed before it returns.
+ * Errors: SBFEM_EINVAL (assembly or precision, k < 1, block outside [k, min(free dofs, 512)],
+ * max_iter < 1, tol <= 0), SBFEM_ENOMEM, SBFEM_EDEVICE, SBFEM_ENOTCONV (host_omega then holds
+ * the last estimates).  The step state of the mesh is not touched.
+ */
+sbfem_status sbfem_eigen_lowest(sbfem_mesh* m, int32_t k, int32_t block, int32_t degree, int32_t max_iter, double tol,
+                                double* host_omega, double* host_resid, int32_t* iterations, void* hip_stream);
 
 /*
  * Kernel timing for diagnostics.  With profiling enabled, every kernel launch

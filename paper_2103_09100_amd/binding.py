@@ -28,7 +28,7 @@ except ImportError:
 
 _lib = C.CDLL(LIB_PATH)
 
-OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTCONV = 0, -1, -2, -3, -4, -5, -6
 PROD = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 STATE = {"fp64": 0, "fp32": 1, "kahan32": 2}
 ASM = {"atomic": 0, "colour": 1, "tiled": 2}
@@ -37,7 +37,8 @@ LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
 EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint",
            "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n", "sbfem_set_graph_steps",
            "sbfem_step_batch", "sbfem_step_batch_noalloc", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
-           "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_set_allocator",
+           "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_set_allocator", "sbfem_eigen_lowest",
+           "sbfem_set_probes", "sbfem_read_probes",
            "sbfem_last_error"]
 KERNEL_CLASSES = ("load", "element_8node", "element_larger", "update")
 
@@ -78,6 +79,10 @@ _lib.sbfem_mesh_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
 _lib.sbfem_profile.argtypes = [_P, C.c_int32]
 _lib.sbfem_profile_read.argtypes = [_P, _P, _P]
 _lib.sbfem_mesh_layout.argtypes = [_P, _P, C.c_int32]
+_lib.sbfem_eigen_lowest.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _P, _P,
+                                     C.POINTER(C.c_int32), _P]
+_lib.sbfem_set_probes.argtypes = [_P, C.c_int32, _P, C.c_int64, _P]
+_lib.sbfem_read_probes.argtypes = [_P, _P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _P]
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 _lib.sbfem_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, _P]
@@ -251,6 +256,35 @@ class Mesh:
         n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
         _check(_lib.sbfem_profile_read(self.handle, ms.ctypes.data, n.ctypes.data))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def set_probes(self, dofs, capacity, stream=None):
+        """sbfem_set_probes: record u_{n+1} and the acceleration of step n at these dofs."""
+        d = np.ascontiguousarray(dofs, dtype=np.int64)
+        self._probe_count = len(d)
+        _check(_lib.sbfem_set_probes(self.handle, len(d), d.ctypes.data if len(d) else None, int(capacity),
+                                     _stream(stream)))
+
+    def read_probes(self, stream=None):
+        """sbfem_read_probes: (u, a, first step), u and a of shape (rows, probes)."""
+        rows, step0 = C.c_int64(), C.c_int64()
+        _check(_lib.sbfem_read_probes(self.handle, None, None, C.byref(rows), C.byref(step0), _stream(stream)))
+        n = getattr(self, "_probe_count", 0)
+        u = np.zeros((rows.value, n))
+        a = np.zeros((rows.value, n))
+        if rows.value and n:
+            _check(_lib.sbfem_read_probes(self.handle, u.ctypes.data, a.ctypes.data, C.byref(rows), C.byref(step0),
+                                          _stream(stream)))
+        return u, a, step0.value
+
+    def eigen_lowest(self, k, block=0, degree=0, max_iter=200, tol=1e-9, stream=None):
+        """sbfem_eigen_lowest: the k smallest circular frequencies, their relative Ritz residuals
+        and the iterations used."""
+        w = np.zeros(k)
+        r = np.zeros(k)
+        it = C.c_int32()
+        _check(_lib.sbfem_eigen_lowest(self.handle, int(k), int(block), int(degree), int(max_iter), float(tol),
+                                       w.ctypes.data, r.ctypes.data, C.byref(it), _stream(stream)))
+        return w, r, it.value
 
     def close(self):
         if self.handle:

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libsbfem.so")
 SOURCES = ["kernels.hip", "mixed_ebe_fp64.hip", "mixed_ebe_fp32.hip", "mixed_tiled_fp64.hip",
            "mixed_tiled_fp32.hip", "mixed_tiled_fp64r.hip", "mixed_tiled_fp32r.hip", "mixed_hang_mma_fp64.hip",
            "mixed_hang_mma_fp32.hip", "mixed_hang_mma_fp16.hip", "mixed_hang_mma_bf16.hip", "owner_fp64.hip", "owner_fp32.hip",
-           "owner_fp16.hip", "owner_bf16.hip", "sbfem.cpp", "tiling.cpp"]
+           "owner_fp16.hip", "owner_bf16.hip", "linalg.hip", "sbfem.cpp", "tiling.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -89,11 +89,19 @@ struct TiledArgs {
   const float* Ws32;    // (16-bit products: the unscaled table rounded to 16 bits, s_e in the last entry)
   const void* u;        // u_n        (state storage, see `state`)
   void* um1;            // u_{n-1} in, u_{n+1} out (owned nodes)
-  const void* minv;     // inverse lumped mass per node (FP64, or FP32 with FP32 state); sign bit set:
-                        // 1 + the position of the node's three values in minv_exc
-  const void* minv_exc; // three values per node whose inverse masses differ (same storage)
+  const void* minv;     // inverse lumped mass per dof (FP64, or FP32 with FP32 state; 0 on fixed dofs)
   double* f;            // force-only mode: R_int of owned dofs written here
   unsigned long long* flag;    // smallest step n whose update gave a non-finite u_{n+1} (~0: none)
+  // probe histories (n_probes = 0: none): tile t records the entries [probe_ptr[t], probe_ptr[t+1])
+  // of `probes` (x: 3 * local owned node + axis, y: probe slot); step n's u_{n+1} and
+  // (u_{n+1} - 2 u_n + u_{n-1}) / dt^2 go to row n - probe_step0 (< probe_rows) of probe_u, probe_a
+  const int32_t* probe_ptr;
+  const int2* probes;
+  double* probe_u;
+  double* probe_a;
+  int64_t probe_step0;
+  int64_t probe_rows;
+  int32_t n_probes;
   const HangItem* hitems;      // hanging-cell pass
   const int32_t* hconn;
   const uint8_t* horient;
@@ -229,5 +237,18 @@ hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t s);
 // refs[0..n): step += steps, parity flipped when steps is odd (graph-safe: a kernel)
 hipError_t launch_refs_advance(MeshRef* refs, int32_t n, int64_t steps, hipStream_t s);
 hipError_t launch_ref_set(MeshRef* ref, const MeshRef& v, hipStream_t s);
+
+// Dense kernels of the eigenvalue solver: n x p blocks stored column after column, FP64;
+// reductions in a fixed order.
+hipError_t launch_gram(const double* X, const double* Y, int64_t n, int p, double* G, hipStream_t s);  // G = X^T Y
+hipError_t launch_gemm_small(const double* X, int64_t n, int p, const double* Q, int q, double* Y,
+                             hipStream_t s);                                                      // Y = X Q
+hipError_t launch_scale_cols(const double* S, const double* X, double* Y, int64_t n, int p, hipStream_t s);
+hipError_t launch_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n, hipStream_t s);
+hipError_t launch_axpbypcz(double a, const double* x, double b, const double* y, double c, double* z, int64_t n,
+                           hipStream_t s);
+hipError_t launch_vmul(const double* sc, const double* x, double* y, int64_t n, hipStream_t s);
+hipError_t launch_ritz_residual(const double* X, const double* AX, int64_t n, int p, const double* theta,
+                                double* out, hipStream_t s);  // out[j] = |AX_j - theta_j X_j|^2
 
 }  // namespace sbfem

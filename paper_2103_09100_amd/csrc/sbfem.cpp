@@ -172,13 +172,13 @@ struct sbfem_patterns {
   float* dK32 = nullptr;
   float* dK16 = nullptr;   // K rounded to FP16, held in FP32 (16-bit product operands)
   float* dKb16 = nullptr;  // K rounded to BF16, held in FP32
-  // 8-node pattern in the corner Walsh basis (8 blocks of 3x3), if its matrix has that structure
-  int64_t walsh_koff = -1;
-  // the 8-node pattern when its matrix is also invariant under the 48 cube transformations:
-  // its cells are then mapped onto it in identity orientation and take the Walsh path with
-  // the structured table Wc (sbfem::kWalshC entries, layout as in the device code)
-  int32_t p8 = -1;
-  std::vector<double> Wc;
+  // 8-node patterns (one per Poisson-ratio library) whose matrix has the block structure of the
+  // corner Walsh basis and is invariant under the 48 cube transformations: their cells are
+  // mapped onto them in identity orientation and take the Walsh path with a structured table
+  // (sbfem::kWalshC entries, layout as in the device code).  walsh_id[pattern]: index of the
+  // pattern's table in Wcs, -1 for every other pattern.
+  std::vector<int16_t> walsh_id;
+  std::vector<std::vector<double>> Wcs;
 };
 
 struct sbfem_mesh {
@@ -192,8 +192,7 @@ struct sbfem_mesh {
   void* u = nullptr;     // state storage per state_mode: FP64, FP32 or compensated FP32 pair
   void* um1 = nullptr;
   double* f = nullptr;
-  void* minv = nullptr;  // per dof (classic assemblies, FP64); per node (owner tiles, see TiledArgs)
-  void* minv_exc = nullptr;  // owner tiles: three values per node whose inverse masses differ
+  void* minv = nullptr;  // per dof: FP64, or FP32 with FP32 state
   double* matE = nullptr;
   int32_t* conn = nullptr;
   uint8_t* orient = nullptr;
@@ -219,6 +218,16 @@ struct sbfem_mesh {
   // internal node numbering (first touch along the cell order)
   std::vector<int32_t> int2ext;
   std::vector<double> mdiag;  // lumped diagonal mass (internal numbering), for read_state
+  std::vector<bool> fixed;    // Dirichlet dofs (internal numbering)
+  double lambda_bound = 0.0;  // max over cells of omega_max,e^2: bounds the spectrum of M^-1 K (eq. tcr)
+  int64_t n_res = 0;          // hanging-cell row-force slots
+  // probe histories (sbfem_set_probes)
+  int32_t* probe_ptr = nullptr;
+  int2* probes = nullptr;
+  double* probe_u = nullptr;
+  double* probe_a = nullptr;
+  int64_t probe_step0 = 0, probe_rows = 0;
+  int32_t n_probes = 0;
   // owner tiles
   sbfem::OwnerTile* otiles = nullptr;
   sbfem::CellItem* items = nullptr;
@@ -303,17 +312,12 @@ struct MeshPlan {
   std::vector<int32_t> iconn;         // internal node ids per cell (master order)
   std::vector<uint8_t> orient;        // orientation per cell (8-node cells re-listed in identity)
   std::vector<double> mdiag, minv;    // lumped mass and its inverse (0 on fixed dofs), internal dofs
+  std::vector<bool> fixed;            // Dirichlet dofs, internal numbering
+  double lambda_bound = 0.0;          // max over cells of omega_max,e^2
   std::vector<int64_t> bidx;          // load vector, internal dofs, duplicates merged
   std::vector<double> bval;
   std::vector<double> matE;           // 256 entries
   bool force_array = false;           // an FP64 force array over all dofs is allocated
-  // owner tiles: inverse mass per node (bits of the FP64 value, or FP32 with FP32 state); a node
-  // whose three values differ has the sign bit set and 1 + its position in the exception table
-  std::vector<uint64_t> mnode64;
-  std::vector<uint32_t> mnode32;
-  std::vector<double> mexc64;
-  std::vector<float> mexc32;
-  int64_t n_exc = 0;
   // owner tiles
   sbfem::TilingOutput to;
   int32_t lds_bytes = 0, block_threads = 512, block_threads_mixed = 256;
@@ -343,13 +347,7 @@ void for_each_buffer(const MeshPlan& P, const sbfem_mesh_desc* d, sbfem_mesh* m,
   const int64_t ndof = P.ndof;
   f(slot(&sbfem_mesh::u), (size_t)state_bytes(d->state, ndof));
   f(slot(&sbfem_mesh::um1), (size_t)state_bytes(d->state, ndof));
-  const size_t mval = d->state == SBFEM_STATE_FP32 ? 4 : 8;
-  if (d->assembly == SBFEM_ASM_TILED) {
-    f(slot(&sbfem_mesh::minv), (size_t)P.N * mval);
-    f(slot(&sbfem_mesh::minv_exc), (size_t)(3 * P.n_exc) * mval);
-  } else {
-    f(slot(&sbfem_mesh::minv), (size_t)ndof * 8);
-  }
+  f(slot(&sbfem_mesh::minv), (size_t)ndof * (d->state == SBFEM_STATE_FP32 ? 4 : 8));
   if (P.force_array) f(slot(&sbfem_mesh::f), (size_t)(ndof * 8));
   f(slot(&sbfem_mesh::matE), 256 * 8);
   f(slot(&sbfem_mesh::flag_d), sizeof(unsigned long long));
@@ -430,9 +428,9 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
   // applies to the cell's own corner order and no transformation is needed per step.
   P.orient.assign(d->orient, d->orient + C);
   std::vector<uint8_t>& orient = P.orient;
-  if (p->p8 >= 0) {
+  if (!p->Wcs.empty()) {
     for (int64_t c = 0; c < C; ++c) {
-      if (d->pattern[c] != p->p8 || orient[c] == 0) continue;
+      if (p->walsh_id[d->pattern[c]] < 0 || orient[c] == 0) continue;
       int pi[3], nat[8];
       double sg[3];
       decode(orient[c], pi, sg);
@@ -456,15 +454,24 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
       for (int a = 0; a < 3; ++a) P.mdiag[3 * (int64_t)iconn[cptr[c] + k] + pi[a]] += sc * mp[3 * k + a];
   }
   P.minv.resize(ndof);
+  P.fixed.assign(ndof, false);
   for (int64_t i = 0; i < ndof; ++i) {
     const int64_t e = 3 * (int64_t)P.int2ext[i / 3] + i % 3;
     if (d->fixed_dof && d->fixed_dof[e]) {
+      P.fixed[i] = true;
       P.minv[i] = 0.0;
     } else {
       if (!(P.mdiag[i] > 0))
         return fail(SBFEM_EINVAL, "free dof %lld has no mass (node not used by any cell?)", (long long)e);
       P.minv[i] = 1.0 / P.mdiag[i];
     }
+  }
+
+  // element bound of the spectrum: omega_max,e = omega_p sqrt(E/rho) / h (eqs. tcr, tcr_scale)
+  for (int64_t c = 0; c < C; ++c) {
+    const double h = std::ldexp(d->h0, -(int)d->level[c]);
+    const double w = p->omega[d->pattern[c]];
+    P.lambda_bound = std::max(P.lambda_bound, w * w * d->E[d->material[c]] / (d->rho[d->material[c]] * h * h));
   }
 
   // load vector (internal dofs) with merged duplicates
@@ -484,35 +491,6 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
   for (int i = 0; i < d->n_materials; ++i) P.matE[i] = d->E[i];
   // the owner-tile step keeps no force array; the start-up with u0 needs one (K u0)
   P.force_array = d->assembly != SBFEM_ASM_TILED || d->u0 != nullptr;
-  if (d->assembly == SBFEM_ASM_TILED) {
-    // inverse mass per node; a node whose three stored values differ goes to the exception table
-    const bool f32 = d->state == SBFEM_STATE_FP32;
-    if (f32)
-      P.mnode32.resize(N);
-    else
-      P.mnode64.resize(N);
-    for (int64_t n = 0; n < N; ++n) {
-      const double* mi = P.minv.data() + 3 * n;
-      if (f32) {
-        const float v0 = (float)mi[0], v1 = (float)mi[1], v2 = (float)mi[2];
-        if (v0 == v1 && v1 == v2) {
-          std::memcpy(&P.mnode32[n], &v0, 4);
-        } else {
-          if (P.n_exc + 1 >= (int64_t)0x7FFFFFFF) return fail(SBFEM_EINVAL, "too many nodes with direction-dependent masses");
-          P.mexc32.insert(P.mexc32.end(), {v0, v1, v2});
-          P.mnode32[n] = 0x80000000u | (uint32_t)(++P.n_exc);
-        }
-      } else {
-        if (mi[0] == mi[1] && mi[1] == mi[2]) {
-          std::memcpy(&P.mnode64[n], &mi[0], 8);
-        } else {
-          P.mexc64.insert(P.mexc64.end(), {mi[0], mi[1], mi[2]});
-          P.mnode64[n] = 0x8000000000000000ull | (uint64_t)(++P.n_exc);
-        }
-      }
-    }
-  }
-
   if (d->assembly == SBFEM_ASM_TILED) {
     sbfem::TilingInput ti;
     ti.n_nodes = N;
@@ -552,7 +530,8 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
     threads_desc(d->block_threads_mixed, P.block_threads_mixed);
     if (d->tile_nodes > 0) tn0 = std::max(32, d->tile_nodes);
     if (const char* ev = std::getenv("SBFEM_DENSE8")) P.walsh = std::atoi(ev) == 0;
-    ti.p8 = P.walsh ? p->p8 : -1;
+    ti.regular = P.walsh && !p->Wcs.empty() ? p->walsh_id.data() : nullptr;
+    auto regular = [&](int64_t c) { return ti.regular && ti.regular[d->pattern[c]] >= 0; };
     bool ok = false;
     // LDS per block: FP64 forces of the owned nodes, u of the local nodes (FP64: 24 B per node;
     // FP32: 16-byte float4 nodes)
@@ -572,7 +551,7 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
     // to a wave of cells of one pattern, in cell order within a pattern; node ids slot-major
     std::vector<int64_t> hcells;
     for (int64_t c = 0; c < C; ++c)
-      if (ti.p8 < 0 || d->pattern[c] != ti.p8) hcells.push_back(c);
+      if (!regular(c)) hcells.push_back(c);
     std::stable_sort(hcells.begin(), hcells.end(),
                      [&](int64_t x, int64_t y) { return d->pattern[x] < d->pattern[y]; });
     // the items of one hanging-pass block share a pattern: each pattern's items are padded with
@@ -648,16 +627,15 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
     for (const auto& it : to.items) P.layout[4] += it.count;
     P.layout[5] = to.tile_nodes;
     // algorithmic bytes per step of each pass (the method's own traffic, whatever the layout):
-    // the owner-tile pass reads u_n, u_{n-1} and writes u_{n+1} of every dof (in the state
-    // storage: 8 B per value for FP64 and the compensated pair, 4 B for FP32), reads the
-    // inverse mass (one value per node, three for a node whose values differ; 8 B, 4 B with
-    // FP32 state), the node ids (4 B each) and orientation, level, material (1 B each) of the
-    // regular 8-node cells, and the load entries (16 B); the hanging-cell pass the same
-    // per-cell bytes of the other cells
+    // the owner-tile pass reads u_n, u_{n-1}, M^-1 and writes u_{n+1} of every dof (in the
+    // state storage: 8 B per value for FP64 and the compensated pair, 4 B for FP32, with M^-1
+    // in FP32 beside FP32 state), the node ids (4 B each) and orientation, level, material
+    // (1 B each) of the regular 8-node cells, and the load entries (16 B); the hanging-cell
+    // pass the same per-cell bytes of the other cells
     {
       const int64_t bs = d->state == SBFEM_STATE_FP32 ? 4 : 8;
-      int64_t b8 = 3 * bs * ndof + bs * (N + 3 * P.n_exc) + 16 * (int64_t)P.bidx.size(), bo = 0;
-      for (int64_t c = 0; c < C; ++c) (ti.p8 >= 0 && d->pattern[c] == ti.p8 ? b8 : bo) += 4 * (cptr[c + 1] - cptr[c]) + 3;
+      int64_t b8 = 4 * bs * ndof + 16 * (int64_t)P.bidx.size(), bo = 0;
+      for (int64_t c = 0; c < C; ++c) (regular(c) ? b8 : bo) += 4 * (cptr[c + 1] - cptr[c]) + 3;
       P.layout[6] = b8;
       P.layout[7] = bo;
     }
@@ -669,16 +647,17 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
     P.ws64.assign(std::max<size_t>(1, ncls) * WC, 0.0);
     P.ws32.assign(P.ws64.size(), 0.0f);
     for (size_t c = 0; c < ncls; ++c) {
-      const int lev = to.scale_keys[c] >> 8, mat = to.scale_keys[c] & 255;
+      const int wid = to.scale_keys[c] >> 16, lev = (to.scale_keys[c] >> 8) & 255, mat = to.scale_keys[c] & 255;
+      const std::vector<double>& Wc = p->Wcs[wid];
       const double se = d->E[mat] * std::ldexp(d->h0, -lev);
       for (int i = 0; i < WC; ++i) {
-        P.ws64[WC * c + i] = se * p->Wc[i];
+        P.ws64[WC * c + i] = se * Wc[i];
         P.ws32[WC * c + i] = (float)P.ws64[WC * c + i];
       }
       if (d->prod == SBFEM_PROD_FP16 || d->prod == SBFEM_PROD_BF16) {
         // 16-bit operands: the unscaled coefficients rounded to 16 bits, s_e applied after
         for (int i = 0; i < WC - 1; ++i)
-          P.ws32[WC * c + i] = d->prod == SBFEM_PROD_FP16 ? round_fp16((float)p->Wc[i]) : round_bf16((float)p->Wc[i]);
+          P.ws32[WC * c + i] = d->prod == SBFEM_PROD_FP16 ? round_fp16((float)Wc[i]) : round_bf16((float)Wc[i]);
         P.ws32[WC * c + WC - 1] = (float)se;
       }
     }
@@ -816,9 +795,10 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
   // Walsh blocks of the 8-node pattern: Khat[(a',s'),(a,s)] = 1/64 sum_{k,k'} chi_s'(k) K[3k+a'][3k'+a] chi_s(k'),
   // corner k = i + 2j + 4l at (2i-1, 2j-1, 2l-1), chi_s(k) = prod_b p_b^(s_b); used only if every
   // entry outside the blocks s' = t^(1<<a'), s = t^(1<<a) vanishes to roundoff.
-  std::vector<double> W(72, 0.0);
+  p->walsh_id.assign(n_patterns, -1);
   for (int pid = 0; pid < n_patterns; ++pid) {
     if (p->ndof[pid] != 24) continue;
+    std::vector<double> W(72, 0.0);
     const double* Kp = p->K.data() + p->koff[pid];
     auto chi = [](int k, int s) {
       double v = 1.0;
@@ -842,7 +822,7 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
             else
               off = std::max(off, std::fabs(v));
           }
-    if (off <= 1e-12 * kmax / 8.0) p->walsh_koff = p->koff[pid];
+    const bool blocks = off <= 1e-12 * kmax / 8.0;
     // invariance under every transformation g:  K[3k+a][3k'+a'] = s_a s_a' K[3n(k)+pi(a)][3n(k')+pi(a')],
     // where corner k of the master sits at corner n(k) of the cell (Sec. 3.2.2)
     double dev = 0.0;
@@ -889,11 +869,10 @@ sbfem_status sbfem_upload_patterns(sbfem_patterns** out, int32_t n_patterns, con
       for (int q = 0; q < 4; ++q) Wc[4 + 4 * mm + q] = b1[q];
       for (int q = 0; q < 5; ++q) Wc[16 + 5 * mm + q] = b2[q];
     }
-    if (p->walsh_koff >= 0 && dev <= 1e-12 * kmax && werr <= 1e-12 * wmax) {
-      p->p8 = pid;
-      p->Wc = Wc;
+    if (blocks && dev <= 1e-12 * kmax && werr <= 1e-12 * wmax && p->Wcs.size() < 32767) {
+      p->walsh_id[pid] = (int16_t)p->Wcs.size();
+      p->Wcs.push_back(Wc);
     }
-    break;
   }
   hipStream_t s = (hipStream_t)hip_stream;
   hipError_t e = hipGetDevice(&p->device);
@@ -1021,7 +1000,6 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->alloc, m->um1);
   dfree(m->alloc, m->f);
   dfree(m->alloc, m->minv);
-  dfree(m->alloc, m->minv_exc);
   dfree(m->alloc, m->matE);
   dfree(m->alloc, m->conn);
   dfree(m->alloc, m->orient);
@@ -1046,6 +1024,10 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->alloc, m->hres);
   dfree(m->alloc, m->dWs64);
   dfree(m->alloc, m->dWs32);
+  dfree(m->alloc, m->probe_ptr);
+  dfree(m->alloc, m->probes);
+  dfree(m->alloc, m->probe_u);
+  dfree(m->alloc, m->probe_a);
   delete m;
 }
 
@@ -1112,9 +1094,15 @@ static sbfem::TiledArgs tiled_args_for(const sbfem_mesh* m, const void* u, void*
   a.u = u;
   a.um1 = um1;
   a.minv = m->minv;
-  a.minv_exc = m->minv_exc;
   a.f = m->f;
   a.flag = m->flag_d;
+  a.probe_ptr = m->probe_ptr;
+  a.probes = m->probes;
+  a.probe_u = m->probe_u;
+  a.probe_a = m->probe_a;
+  a.probe_step0 = m->probe_step0;
+  a.probe_rows = m->probe_rows;
+  a.n_probes = m->n_probes;
   a.ndof = m->ndof;
   a.state = m->state_mode;
   a.round16 = m->prod == SBFEM_PROD_FP16 ? 1 : (m->prod == SBFEM_PROD_BF16 ? 2 : 0);
@@ -1239,14 +1227,10 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
     H2D(m->load_idx, P.bidx.data(), P.bidx.size() * 8);
     H2D(m->load_val, P.bval.data(), P.bval.size() * 8);
   }
-  if (d->assembly == SBFEM_ASM_TILED) {
-    if (d->state == SBFEM_STATE_FP32) {
-      H2D(m->minv, P.mnode32.data(), P.mnode32.size() * 4);
-      H2D(m->minv_exc, P.mexc32.data(), P.mexc32.size() * 4);
-    } else {
-      H2D(m->minv, P.mnode64.data(), P.mnode64.size() * 8);
-      H2D(m->minv_exc, P.mexc64.data(), P.mexc64.size() * 8);
-    }
+  std::vector<float> minv32;
+  if (d->state == SBFEM_STATE_FP32) {
+    minv32.assign(P.minv.begin(), P.minv.end());
+    H2D(m->minv, minv32.data(), ndof * 4);
   } else {
     H2D(m->minv, P.minv.data(), ndof * 8);
   }
@@ -1308,7 +1292,21 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   }
   m->int2ext.swap(P.int2ext);
   m->mdiag.swap(P.mdiag);
+  m->fixed.swap(P.fixed);
+  m->lambda_bound = P.lambda_bound;
+  m->n_res = P.n_res;
   *out = m;
+  return SBFEM_OK;
+}
+
+// Argument blocks of the owner-tile launches re-uploaded after a change of the mesh's buffers.
+static sbfem_status upload_tiled_args(sbfem_mesh* m, hipStream_t s) {
+  const bool swapped = m->u != m->buf0;
+  void* b0 = m->buf0;
+  void* b1 = swapped ? m->u : m->um1;
+  const sbfem::TiledArgs ta[2] = {tiled_args_for(m, b0, b1), tiled_args_for(m, b1, b0)};
+  HIP_TRY(hipMemcpyAsync(m->d_args, ta, sizeof(ta), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return SBFEM_OK;
 }
 
@@ -1318,14 +1316,7 @@ static sbfem_status ensure_force_array(sbfem_mesh* m, hipStream_t s) {
   if (m->f) return SBFEM_OK;
   HIP_TRY(dalloc(m->alloc, &m->f, (size_t)m->ndof));
   m->bytes += m->ndof * 8;
-  if (m->assembly == SBFEM_ASM_TILED) {
-    const bool swapped = m->u != m->buf0;
-    void* b0 = m->buf0;
-    void* b1 = swapped ? m->u : m->um1;
-    const sbfem::TiledArgs ta[2] = {tiled_args_for(m, b0, b1), tiled_args_for(m, b1, b0)};
-    HIP_TRY(hipMemcpyAsync(m->d_args, ta, sizeof(ta), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
+  if (m->assembly == SBFEM_ASM_TILED) return upload_tiled_args(m, s);
   return SBFEM_OK;
 }
 
@@ -1838,3 +1829,339 @@ sbfem_status sbfem_mesh_info(const sbfem_mesh* m, int64_t* device_bytes, int64_t
 }
 
 }  // extern "C"
+
+extern "C" sbfem_status sbfem_set_probes(sbfem_mesh* m, int32_t n_probes, const int64_t* dofs, int64_t capacity,
+                                         void* hip_stream) {
+  if (!m) return fail(SBFEM_EINVAL, "null mesh");
+  if (n_probes < 0 || capacity < 0 || (n_probes > 0 && !dofs)) return fail(SBFEM_EINVAL, "bad probe arguments");
+  if (n_probes > 0 && m->assembly != SBFEM_ASM_TILED) return fail(SBFEM_EINVAL, "probes need the owner-tile assembly");
+  for (int32_t i = 0; i < n_probes; ++i)
+    if (dofs[i] < 0 || dofs[i] >= m->ndof) return fail(SBFEM_EINVAL, "probe %d: dof out of range", i);
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipStreamSynchronize(s));  // launches in flight may still read the old buffers
+  dfree(m->alloc, m->probe_ptr);
+  dfree(m->alloc, m->probes);
+  dfree(m->alloc, m->probe_u);
+  dfree(m->alloc, m->probe_a);
+  m->n_probes = 0;
+  m->probe_rows = 0;
+  if (n_probes > 0) {
+    std::vector<int32_t> ext2int(m->N);
+    for (int64_t i = 0; i < m->N; ++i) ext2int[m->int2ext[i]] = (int32_t)i;
+    const int64_t n_tiles = m->n_pure8 + m->n_mixed;
+    std::vector<std::vector<int2>> per(n_tiles);
+    for (int32_t i = 0; i < n_probes; ++i) {
+      const int64_t node = ext2int[dofs[i] / 3];
+      const int64_t t = node / m->tile_nodes;
+      per[t].push_back(make_int2((int)(3 * (node - t * m->tile_nodes) + dofs[i] % 3), i));
+    }
+    std::vector<int32_t> ptr(n_tiles + 1, 0);
+    std::vector<int2> ent;
+    for (int64_t t = 0; t < n_tiles; ++t) {
+      ent.insert(ent.end(), per[t].begin(), per[t].end());
+      ptr[t + 1] = (int32_t)ent.size();
+    }
+    const size_t hist = (size_t)std::max<int64_t>(1, capacity) * n_probes;
+    hipError_t e = dalloc(m->alloc, &m->probe_ptr, ptr.size());
+    if (e == hipSuccess) e = dalloc(m->alloc, &m->probes, ent.size());
+    if (e == hipSuccess) e = dalloc(m->alloc, &m->probe_u, hist);
+    if (e == hipSuccess) e = dalloc(m->alloc, &m->probe_a, hist);
+    if (e == hipSuccess) e = hipMemcpyAsync(m->probe_ptr, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(m->probes, ent.data(), ent.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      dfree(m->alloc, m->probe_ptr);
+      dfree(m->alloc, m->probes);
+      dfree(m->alloc, m->probe_u);
+      dfree(m->alloc, m->probe_a);
+      return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "probes: %s", hipGetErrorString(e));
+    }
+    m->n_probes = n_probes;
+    m->probe_rows = capacity;
+    m->probe_step0 = m->step;
+  }
+  return upload_tiled_args(m, s);
+}
+
+extern "C" sbfem_status sbfem_read_probes(sbfem_mesh* m, double* host_u, double* host_a, int64_t* rows,
+                                          int64_t* step0, void* hip_stream) {
+  if (!m) return fail(SBFEM_EINVAL, "null mesh");
+  const int64_t r = std::max<int64_t>(0, std::min(m->probe_rows, m->step - m->probe_step0));
+  if (rows) *rows = m->n_probes ? r : 0;
+  if (step0) *step0 = m->probe_step0;
+  if (m->n_probes == 0 || r == 0) return SBFEM_OK;
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t bytes = (size_t)r * m->n_probes * 8;
+  if (host_u) HIP_TRY(hipMemcpyAsync(host_u, m->probe_u, bytes, hipMemcpyDeviceToHost, s));
+  if (host_a) HIP_TRY(hipMemcpyAsync(host_a, m->probe_a, bytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return check_flag(m);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Lowest eigenfrequencies of the free vibration K phi = omega^2 M phi (Sec. 5.1): Chebyshev-
+// filtered subspace iteration on A = S K S, S = diag(M^-1/2) with S = 0 on fixed dofs, whose
+// eigenvalues over the free dofs are omega^2.  K is applied by the owner-tile pass in force-only
+// mode to a whole block of vectors in one batched launch (one argument block per vector).
+
+namespace {
+
+// Symmetric eigen-decomposition of a small dense matrix by cyclic Jacobi rotations.  A is n x n
+// row-major and is overwritten; w receives the eigenvalues ascending and V (row-major) the
+// eigenvectors as columns in the same order.
+void jacobi_eigen(std::vector<double> A, int n, std::vector<double>& w, std::vector<double>& V) {
+  std::vector<double> Q(n * (size_t)n, 0.0);
+  for (int i = 0; i < n; ++i) Q[i * (size_t)n + i] = 1.0;
+  double total = 0.0;
+  for (double v : A) total += v * v;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * (size_t)n + j] * A[i * (size_t)n + j];
+    if (off <= 1e-32 * total) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * (size_t)n + q];
+        if (apq == 0.0) continue;
+        const double app = A[p * (size_t)n + p], aqq = A[q * (size_t)n + q];
+        // rotation angle that zeroes A[p][q]: tan(2 phi) = 2 apq / (aqq - app)
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(tau * tau + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = A[k * (size_t)n + p], akq = A[k * (size_t)n + q];
+          A[k * (size_t)n + p] = c * akp - s * akq;
+          A[k * (size_t)n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = A[p * (size_t)n + k], aqk = A[q * (size_t)n + k];
+          A[p * (size_t)n + k] = c * apk - s * aqk;
+          A[q * (size_t)n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double qkp = Q[k * (size_t)n + p], qkq = Q[k * (size_t)n + q];
+          Q[k * (size_t)n + p] = c * qkp - s * qkq;
+          Q[k * (size_t)n + q] = s * qkp + c * qkq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[a * (size_t)n + a] < A[b * (size_t)n + b]; });
+  w.resize(n);
+  V.assign(n * (size_t)n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    w[j] = A[idx[j] * (size_t)n + idx[j]];
+    for (int i = 0; i < n; ++i) V[i * (size_t)n + j] = Q[i * (size_t)n + idx[j]];
+  }
+}
+
+}  // namespace
+
+// Work of one eigenvalue solve: p argument blocks (one per column of the block), the work
+// lists of the batched force-only launches over (column, tile) and (column, item), and the
+// dense blocks (n x p, column-major) of the iteration.
+struct EigenWork {
+  Allocator alloc;
+  int64_t n = 0;
+  int p = 0;
+  sbfem::TiledArgs* d_args = nullptr;  // p argument blocks
+  sbfem::MeshRef* d_refs = nullptr;
+  sbfem::TileWork* d_w8 = nullptr;
+  sbfem::TileWork* d_wm = nullptr;
+  int64_t n8 = 0, nm = 0;
+  double* S = nullptr;                 // M^-1/2 per dof, 0 on fixed dofs
+  double *X = nullptr, *AX = nullptr, *Y0 = nullptr, *Y1 = nullptr, *W = nullptr, *F = nullptr;
+  void* hres = nullptr;                // hanging-cell row forces, one slice per column
+  double *G = nullptr, *H = nullptr, *Q = nullptr, *theta = nullptr, *res = nullptr;
+  ~EigenWork() {
+    for (void** q : {(void**)&d_args, (void**)&d_refs, (void**)&d_w8, (void**)&d_wm, (void**)&S, (void**)&X,
+                     (void**)&AX, (void**)&Y0, (void**)&Y1, (void**)&W, (void**)&F, (void**)&hres, (void**)&G,
+                     (void**)&H, (void**)&Q, (void**)&theta, (void**)&res})
+      if (*q) {
+        if (alloc.release)
+          alloc.release(*q, alloc.user);
+        else
+          (void)hipFree(*q);
+        *q = nullptr;
+      }
+  }
+};
+
+// y = S .* x for every column of an n x p block; the operator's element pass in between
+static hipError_t eigen_apply(EigenWork& W, const sbfem::TiledLaunch& L, const double* X, double* Y, hipStream_t s) {
+  hipError_t e = sbfem::launch_scale_cols(W.S, X, W.W, W.n, W.p, s);
+  if (e == hipSuccess) e = sbfem::launch_tiled(L, s);
+  if (e == hipSuccess) e = sbfem::launch_scale_cols(W.S, W.F, Y, W.n, W.p, s);
+  return e;
+}
+
+extern "C" sbfem_status sbfem_eigen_lowest(sbfem_mesh* m, int32_t k, int32_t block, int32_t degree, int32_t max_iter,
+                                           double tol, double* host_omega, double* host_resid, int32_t* iterations,
+                                           void* hip_stream) {
+  if (!m || !host_omega) return fail(SBFEM_EINVAL, "null argument");
+  if (m->assembly != SBFEM_ASM_TILED || m->prod != SBFEM_PROD_FP64 || m->state_mode != SBFEM_STATE_FP64)
+    return fail(SBFEM_EINVAL, "the eigenvalue solver needs the owner-tile assembly with FP64 products and state");
+  if (k < 1 || max_iter < 1 || !(tol > 0)) return fail(SBFEM_EINVAL, "bad k, max_iter or tol");
+  const int64_t n = m->ndof;
+  int64_t n_free = 0;
+  for (int64_t i = 0; i < n; ++i) n_free += m->fixed[i] ? 0 : 1;
+  const int p = block > 0 ? block : k + std::max(16, k / 2);
+  if (p < k || p > n_free || p > 512) return fail(SBFEM_EINVAL, "block %d must lie in [k, min(free dofs, 512)]", p);
+  const int d = degree > 0 ? degree : 20;
+  HIP_TRY(hipSetDevice(m->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  EigenWork W;
+  W.alloc = m->alloc;
+  W.n = n;
+  W.p = p;
+  const int64_t np = n * p;
+  const int64_t n_tiles = m->n_pure8 + m->n_mixed;
+  const size_t rbytes = (size_t)std::max<int64_t>(1, m->n_res) * 8;
+  hipError_t e = hipSuccess;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = dalloc_bytes(W.alloc, ptr, bytes);
+  };
+  A((void**)&W.d_args, p * sizeof(sbfem::TiledArgs));
+  A((void**)&W.d_refs, p * sizeof(sbfem::MeshRef));
+  A((void**)&W.d_w8, std::max<int64_t>(1, p * n_tiles) * sizeof(sbfem::TileWork));
+  A((void**)&W.d_wm, std::max<int64_t>(1, p * m->n_hang) * sizeof(sbfem::TileWork));
+  A((void**)&W.S, n * 8);
+  for (double** b : {&W.X, &W.AX, &W.Y0, &W.Y1, &W.W, &W.F}) A((void**)b, np * 8);
+  A(&W.hres, rbytes * p);
+  A((void**)&W.G, (size_t)p * p * 8);
+  A((void**)&W.H, (size_t)p * p * 8);
+  A((void**)&W.Q, (size_t)p * p * 8);
+  A((void**)&W.theta, p * 8);
+  A((void**)&W.res, p * 8);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? SBFEM_ENOMEM : SBFEM_EDEVICE, "eigen work: %s",
+                                   hipGetErrorString(e));
+  // argument blocks: column j reads u from W_j, writes R_int to F_j, hanging rows to its slice
+  std::vector<sbfem::TiledArgs> args(p);
+  std::vector<sbfem::MeshRef> refs(p);
+  std::vector<sbfem::TileWork> w8, wm;
+  for (int j = 0; j < p; ++j) {
+    args[j] = tiled_args_for(m, W.W + (int64_t)j * n, nullptr);
+    args[j].f = W.F + (int64_t)j * n;
+    args[j].hres = (char*)W.hres + rbytes * j;
+    refs[j] = sbfem::MeshRef{W.d_args + j, 0, 0, 0};
+    for (int64_t t = 0; t < n_tiles; ++t) w8.push_back({j, 0, t});
+    for (int64_t t = 0; t < m->n_hang; ++t) wm.push_back({j, 0, t});
+  }
+  std::vector<double> S(n);
+  for (int64_t i = 0; i < n; ++i) S[i] = m->fixed[i] ? 0.0 : 1.0 / std::sqrt(m->mdiag[i]);
+  // seeded start block, zero on fixed dofs
+  std::vector<double> X0(np);
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  for (int64_t i = 0; i < np; ++i) {
+    st ^= st << 13, st ^= st >> 7, st ^= st << 17;  // xorshift64
+    X0[i] = m->fixed[i % n] ? 0.0 : (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+  auto H2D = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  H2D(W.d_args, args.data(), p * sizeof(sbfem::TiledArgs));
+  H2D(W.d_refs, refs.data(), p * sizeof(sbfem::MeshRef));
+  H2D(W.d_w8, w8.data(), w8.size() * sizeof(sbfem::TileWork));
+  H2D(W.d_wm, wm.data(), wm.size() * sizeof(sbfem::TileWork));
+  H2D(W.S, S.data(), n * 8);
+  H2D(W.X, X0.data(), np * 8);
+  if (e != hipSuccess) return fail(SBFEM_EDEVICE, "eigen set-up: %s", hipGetErrorString(e));
+  sbfem::TiledLaunch L = tiled_launch(m, true);
+  L.refs = W.d_refs;
+  L.work8 = W.d_w8;
+  L.work_hang = W.d_wm;
+  L.n_tiles = p * n_tiles;
+  L.n_hang = p * m->n_hang;
+  L.k = 0;
+
+  const double lam_hi = 1.01 * m->lambda_bound;  // above the spectrum of A (element bound, eq. tcr)
+  std::vector<double> G(p * (size_t)p), H(p * (size_t)p), lam, U, Qf(p * (size_t)p), th(p, 0.0), rs(p, 0.0);
+  double a_cut = 0.0;
+  int it = 0;
+  bool done = false;
+  for (; it < max_iter && !done; ++it) {
+    if (it > 0) {
+      // Chebyshev filter of degree d damping [a_cut, lam_hi] (Y_{j+1} = 2 (A - c)/e Y_j - Y_{j-1})
+      const double c = 0.5 * (lam_hi + a_cut), eh = 0.5 * (lam_hi - a_cut);
+      // the filter amplifies the lowest Ritz direction by T_d(x0); the degree is held so that
+      // this stays below 1e8 and the block keeps its rank in FP64
+      const double x0 = (c - th[0]) / eh;
+      int dg = d;
+      if (x0 > 1.0) dg = std::max(1, std::min(d, (int)(std::log(1e8) / std::log(x0 + std::sqrt(x0 * x0 - 1.0)))));
+      double* y0 = W.X;
+      double* y1 = W.Y1;
+      e = eigen_apply(W, L, y0, W.AX, s);
+      if (e == hipSuccess) e = sbfem::launch_axpby(1.0 / eh, W.AX, -c / eh, y0, y1, np, s);
+      for (int j = 2; j <= dg && e == hipSuccess; ++j) {
+        // y_j = 2/e (A - c) y_{j-1} - y_{j-2}, written over y_{j-2}
+        e = eigen_apply(W, L, y1, W.AX, s);
+        if (e == hipSuccess) e = sbfem::launch_axpbypcz(2.0 / eh, W.AX, -2.0 * c / eh, y1, -1.0, y0, np, s);
+        std::swap(y0, y1);
+      }
+      // the filtered block (y1) becomes X; y0 is free again
+      W.X = y1;
+      W.Y1 = y0;
+    }
+    // two orthonormalisation passes X <- X U Lambda^-1/2 (G = X^T X = U Lambda U^T); directions
+    // whose Gram eigenvalue falls below 1e-14 of the largest are replaced by fresh seeded
+    // vectors between the passes
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      e = sbfem::launch_gram(W.X, W.X, n, p, W.G, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(G.data(), W.G, G.size() * 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) break;
+      jacobi_eigen(G, p, lam, U);
+      const double thr = 1e-14 * lam.back();
+      std::fill(Qf.begin(), Qf.end(), 0.0);
+      int r = 0;
+      for (int j = 0; j < p; ++j) {
+        if (!(lam[j] > thr)) continue;
+        for (int i = 0; i < p; ++i) Qf[i * (size_t)p + r] = U[i * (size_t)p + j] / std::sqrt(lam[j]);
+        ++r;
+      }
+      if (r == 0) return fail(SBFEM_EDEVICE, "eigen iteration: the block has no independent column");
+      H2D(W.Q, Qf.data(), Qf.size() * 8);
+      if (e == hipSuccess) e = sbfem::launch_gemm_small(W.X, n, p, W.Q, p, W.Y0, s);
+      std::swap(W.X, W.Y0);
+      if (r < p) {
+        for (int64_t i = 0; i < (int64_t)(p - r) * n; ++i) {
+          st ^= st << 13, st ^= st >> 7, st ^= st << 17;
+          X0[i] = m->fixed[i % n] ? 0.0 : (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        H2D(W.X + (int64_t)r * n, X0.data(), (size_t)(p - r) * n * 8);
+      }
+    }
+    // Rayleigh-Ritz: H = X^T A X = Q Theta Q^T, X <- X Q, AX <- AX Q
+    if (e == hipSuccess) e = eigen_apply(W, L, W.X, W.AX, s);
+    if (e == hipSuccess) e = sbfem::launch_gram(W.X, W.AX, n, p, W.H, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(H.data(), W.H, H.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(SBFEM_EDEVICE, "eigen iteration: %s", hipGetErrorString(e));
+    for (int i = 0; i < p; ++i)  // symmetrise (rounding of the products)
+      for (int j = i + 1; j < p; ++j) H[i * (size_t)p + j] = H[j * (size_t)p + i] = 0.5 * (H[i * (size_t)p + j] + H[j * (size_t)p + i]);
+    jacobi_eigen(H, p, th, Qf);
+    H2D(W.Q, Qf.data(), Qf.size() * 8);
+    H2D(W.theta, th.data(), p * 8);
+    if (e == hipSuccess) e = sbfem::launch_gemm_small(W.X, n, p, W.Q, p, W.Y0, s);
+    if (e == hipSuccess) e = sbfem::launch_gemm_small(W.AX, n, p, W.Q, p, W.Y1, s);
+    std::swap(W.X, W.Y0);
+    std::swap(W.AX, W.Y1);
+    const int r = p;
+    if (e == hipSuccess) e = sbfem::launch_ritz_residual(W.X, W.AX, n, std::min(r, p), W.theta, W.res, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(rs.data(), W.res, p * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(SBFEM_EDEVICE, "eigen iteration: %s", hipGetErrorString(e));
+    done = true;
+    for (int j = 0; j < k; ++j) done = done && std::sqrt(std::max(rs[j], 0.0)) <= tol * th[j];
+    a_cut = th[r - 1];
+  }
+  for (int j = 0; j < k; ++j) {
+    host_omega[j] = std::sqrt(std::max(th[j], 0.0));
+    if (host_resid) host_resid[j] = std::sqrt(std::max(rs[j], 0.0)) / std::max(th[j], 1e-300);
+  }
+  if (iterations) *iterations = it;
+  if (!done) return fail(SBFEM_ENOTCONV, "eigenvalues not converged to %g in %d iterations", tol, max_iter);
+  return SBFEM_OK;
+}

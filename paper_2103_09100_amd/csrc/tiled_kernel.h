@@ -262,62 +262,20 @@ __device__ __forceinline__ void tile_hang_forces(const TiledArgs& a, const Owner
   }
 }
 
-// Inverse lumped mass of an owned node (owner-tile layout): one value per node (FP64, FP32 with
-// FP32 state); a node whose three values differ (masses of hanging-node cells, a partly fixed
-// node) has the sign bit set and, in the other bits, 1 + its position in a table of three values
-// per such node.  Fixed dofs have the value 0 (eq. DnMdiag then keeps them at rest).
-template <int STATE>
-struct MinvRaw {
-  using T = uint64_t;
-};
-template <>
-struct MinvRaw<1> {
-  using T = uint32_t;
-};
-template <int STATE>
-__device__ __forceinline__ typename MinvRaw<STATE>::T minv_raw(const TiledArgs& a, int64_t node) {
-  using R = typename MinvRaw<STATE>::T;
-  return as_global((const R*)a.minv)[node];
-}
-template <int STATE>
-__device__ __forceinline__ void minv_decode(const TiledArgs& a, typename MinvRaw<STATE>::T raw, double& m0,
-                                            double& m1, double& m2) {
-  using R = typename MinvRaw<STATE>::T;
-  constexpr R sign = R(1) << (8 * sizeof(R) - 1);
-  if (raw & sign) {
-    const int64_t x = 3 * ((int64_t)(raw & ~sign) - 1);
-    if constexpr (STATE == 1) {
-      const gptr_t<float> e = as_global((const float*)a.minv_exc) + x;
-      m0 = e[0], m1 = e[1], m2 = e[2];
-    } else {
-      const gptr_t<double> e = as_global((const double*)a.minv_exc) + x;
-      m0 = e[0], m1 = e[1], m2 = e[2];
-    }
-  } else {
-    if constexpr (STATE == 1)
-      m0 = (double)__uint_as_float((uint32_t)raw);
-    else
-      m0 = __longlong_as_double((long long)raw);
-    m1 = m2 = m0;
+// Probe histories: if owned dof ldof of the tile is a probe, its u_{n+1} and the central-
+// difference acceleration of step n go to the history row of the step.  [e0, e1): the tile's
+// probe entries (a handful at most, so they are scanned).
+__device__ __forceinline__ void probe_record(const TiledArgs& a, int32_t e0, int32_t e1, int ldof, int64_t step,
+                                             double unew, double un, double up) {
+  for (int32_t e = e0; e < e1; ++e) {
+    const int2 pe = a.probes[e];
+    if (pe.x != ldof) continue;
+    const int64_t row = step - a.probe_step0;
+    if (row < 0 || row >= a.probe_rows) continue;
+    const int64_t o = row * a.n_probes + pe.y;
+    as_global_mut(a.probe_u)[o] = unew;
+    as_global_mut(a.probe_a)[o] = (unew - 2.0 * un + up) / a.dt2;
   }
-}
-
-// the inverse mass of component comp of the node whose raw value this is
-template <int STATE>
-__device__ __forceinline__ double minv_of_dof(const TiledArgs& a, typename MinvRaw<STATE>::T raw, int comp) {
-  using R = typename MinvRaw<STATE>::T;
-  constexpr R sign = R(1) << (8 * sizeof(R) - 1);
-  if (raw & sign) {
-    const int64_t x = 3 * ((int64_t)(raw & ~sign) - 1) + comp;
-    if constexpr (STATE == 1)
-      return (double)as_global((const float*)a.minv_exc)[x];
-    else
-      return as_global((const double*)a.minv_exc)[x];
-  }
-  if constexpr (STATE == 1)
-    return (double)__uint_as_float((uint32_t)raw);
-  else
-    return __longlong_as_double((long long)raw);
 }
 
 // u_{n+1} of one owned node from its forces, u_n, u_{n-1} and inverse mass (eq. DnMdiag),
@@ -325,11 +283,12 @@ __device__ __forceinline__ double minv_of_dof(const TiledArgs& a, typename MinvR
 template <int STATE>
 __device__ __forceinline__ bool node_update(const TiledArgs& a, int64_t node, const double* f, double un0, double un1,
                                             double un2, double up0, double up1, double up2, double m0, double m1,
-                                            double m2) {
+                                            double m2, double (&v)[3]) {
   const double inv = 1.0 / (1.0 + a.c), cm = 1.0 - a.c;
   const double v0 = (a.dt2 * m0 * (-f[0]) + 2.0 * un0 - cm * up0) * inv;
   const double v1 = (a.dt2 * m1 * (-f[1]) + 2.0 * un1 - cm * up1) * inv;
   const double v2 = (a.dt2 * m2 * (-f[2]) + 2.0 * un2 - cm * up2) * inv;
+  v[0] = v0, v[1] = v1, v[2] = v2;
   state_store(a.um1, STATE, a.ndof, 3 * node + 0, v0);
   state_store(a.um1, STATE, a.ndof, 3 * node + 1, v1);
   state_store(a.um1, STATE, a.ndof, 3 * node + 2, v2);
@@ -340,7 +299,7 @@ __device__ __forceinline__ bool node_update(const TiledArgs& a, int64_t node, co
 // node by node, with every operand loaded here (tiles that the block does not cover one node
 // per thread).  un_lds: u_n of the owned dofs as staged (FP64 staging holds u_n itself).
 template <bool FP32, int STATE>
-__device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile& tile, const double* fl,
+__device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile& tile, int64_t ti, const double* fl,
                                             const double* un_lds, int force_only, int64_t step, int tid, int nt) {
   if (force_only) {
     const int64_t d0 = 3 * tile.own0;
@@ -351,15 +310,22 @@ __device__ __forceinline__ void tile_update(const TiledArgs& a, const OwnerTile&
   bool ok = true;
   for (int l = tid; l < tile.n_own; l += nt) {
     const int64_t node = tile.own0 + l;
-    double m0, m1, m2;
-    minv_decode<STATE>(a, minv_raw<STATE>(a, node), m0, m1, m2);
+    const double m0 = minv_load(a.minv, STATE, 3 * node + 0), m1 = minv_load(a.minv, STATE, 3 * node + 1),
+                 m2 = minv_load(a.minv, STATE, 3 * node + 2);
     double un[3], up[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       un[c] = FP32 ? state_load(a.u, STATE, a.ndof, 3 * node + c) : un_lds[3 * l + c];
       up[c] = state_load(a.um1, STATE, a.ndof, 3 * node + c);
     }
-    ok &= node_update<STATE>(a, node, fl + 3 * l, un[0], un[1], un[2], up[0], up[1], up[2], m0, m1, m2);
+    double v[3];
+    ok &= node_update<STATE>(a, node, fl + 3 * l, un[0], un[1], un[2], up[0], up[1], up[2], m0, m1, m2, v);
+    if (a.n_probes) {
+      const int32_t e0 = a.probe_ptr[ti], e1 = a.probe_ptr[ti + 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (e1 > e0) probe_record(a, e0, e1, 3 * l + c, step, v[c], un[c], up[c]);
+    }
   }
   if (!ok) atomicMin(a.flag, (unsigned long long)step);
 }
@@ -583,12 +549,11 @@ __global__ void __launch_bounds__(512, FP32 ? 4 : 1) tiled_hang(MeshRef single, 
 // record feeds the item loop, the loads and the hanging-cell forces.  With `ids` each thread
 // owns one node, whose staged u_n also serves the update.
 template <int PROD, int STATE>
-__device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& tile, int64_t own0, int n_own,
-                                           int64_t step, int force_only, bool ids, int32_t h0, int32_t h1,
+__device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& tile, int64_t ti, int64_t own0,
+                                           int n_own, int64_t step, int force_only, bool ids, int32_t h0, int32_t h1,
                                            double* lds) {
   constexpr bool FP32 = PROD != 0;
   using T = typename LdsType<FP32>::T;
-  using R = typename MinvRaw<STATE>::T;
   double* fl = lds;
   // the staged u starts 16-byte aligned (FP32 staging reads float4 nodes)
   T* ul = (T*)(lds + ((3 * (int64_t)n_own + 1) & ~(int64_t)1));
@@ -597,23 +562,21 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int n_waves = nt >> 6;
   // update operands of the thread's owned dofs tid, tid + nt, tid + 2 nt (consecutive dofs in
-  // consecutive lanes): u_{n-1}, the node's raw inverse mass and, for FP32 products, u_n
+  // consecutive lanes): u_{n-1}, the inverse mass and, for FP32 products, u_n
   constexpr int kPre = 3;
   const int n_dof = 3 * n_own;
   const bool pre = !force_only && n_dof <= kPre * nt;  // uniform
-  double pu[kPre], pp[kPre];
-  R mr[kPre];
+  double pu[kPre], pp[kPre], pm[kPre];
   if (pre) {
     const int64_t d0 = 3 * own0;
 #pragma unroll
     for (int j = 0; j < kPre; ++j) {
       const int i = tid + j * nt;
-      pu[j] = pp[j] = 0.0;
-      mr[j] = 0;
+      pu[j] = pp[j] = pm[j] = 0.0;
       if (i < n_dof) {
         if constexpr (FP32) pu[j] = state_load(a.u, STATE, a.ndof, d0 + i);
         pp[j] = state_load(a.um1, STATE, a.ndof, d0 + i);
-        mr[j] = minv_raw<STATE>(a, own0 + i / 3);
+        pm[j] = minv_load(a.minv, STATE, d0 + i);
       }
     }
   }
@@ -657,16 +620,19 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
     for (int j = 0; j < kPre; ++j) {
       const int i = tid + j * nt;
       if (i < n_dof) {
-        const double m = minv_of_dof<STATE>(a, mr[j], i % 3);
         const double un = FP32 ? pu[j] : (double)ul[i];
-        const double v = (a.dt2 * m * (-fl[i]) + 2.0 * un - cm * pp[j]) * inv;
+        const double v = (a.dt2 * pm[j] * (-fl[i]) + 2.0 * un - cm * pp[j]) * inv;
         state_store(a.um1, STATE, a.ndof, d0 + i, v);
         ok &= state_finite(STATE, v);
+        if (a.n_probes) {  // uniform
+          const int32_t e0 = a.probe_ptr[ti], e1 = a.probe_ptr[ti + 1];
+          if (e1 > e0) probe_record(a, e0, e1, i, step, v, un, pp[j]);
+        }
       }
     }
     if (!ok) atomicMin(a.flag, (unsigned long long)step);
   } else {
-    tile_update<FP32, STATE>(a, tile, fl, (const double*)ul, force_only, step, tid, nt);
+    tile_update<FP32, STATE>(a, tile, ti, fl, (const double*)ul, force_only, step, tid, nt);
   }
 }
 
@@ -697,7 +663,7 @@ __global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef
     if (tid + nt < H) h1 = nl[tid + nt];
   }
   const OwnerTile tile = load_const(as_const(a.tiles) + ti);
-  owner_tile<PROD, STATE>(a, tile, own0, n_own, step, force_only, ids, h0, h1, lds);
+  owner_tile<PROD, STATE>(a, tile, ti, own0, n_own, step, force_only, ids, h0, h1, lds);
 }
 
 }  // namespace sbfem

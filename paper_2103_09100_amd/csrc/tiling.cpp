@@ -2,13 +2,13 @@
 //
 // Nodes carry internal ids in first-touch order along the cell sequence, so a
 // run of consecutive ids is a spatially compact set.  Tile t owns the ids
-// [t*T, (t+1)*T).  Its work is every regular 8-node cell (pattern p8, identity
+// [t*T, (t+1)*T).  Its work is every regular 8-node cell (a pattern with a Walsh table, identity
 // orientation) that touches an owned node; for each such cell only the rows of
 // owned corners are accumulated.  Hanging-node cells are not staged here: they
 // have a pass of their own, whose rows reach the owning tiles as (dof, result)
 // pairs (set up with the mesh).
 //
-// The regular cells form the items: one scale class (level, material) per item
+// The regular cells form the items: one scale class (Walsh table, level, material) per item
 // so the pre-scaled Walsh table is uniform in a wave, full waves of cells in
 // cell (Morton) order (the item's mask is the union of the cells' owned-corner
 // masks), and the eight local node indices of a cell stored together (16 bytes,
@@ -58,14 +58,15 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
     for (int64_t c = 0; c < C; ++c)
       for (int64_t i = in.cptr[c]; i < in.cptr[c + 1]; ++i) ncell[pos[in.conn[i]]++] = (int32_t)c;
   }
-  // scale class of every 8-node cell: (level, material) in order of first use
-  std::vector<int32_t> cls(in.p8 >= 0 ? C : 0, -1);
+  // scale class of every regular cell: (Walsh table, level, material) in order of first use
+  auto is_regular = [&](int64_t c) { return in.regular && in.regular[in.pattern[c]] >= 0; };
+  std::vector<int32_t> cls(in.regular ? C : 0, -1);
   out = TilingOutput();
-  if (in.p8 >= 0) {
+  if (in.regular) {
     std::unordered_map<int32_t, int32_t> seen;
     for (int64_t c = 0; c < C; ++c) {
-      if (in.pattern[c] != in.p8) continue;
-      const int32_t key = (int32_t)in.level[c] * 256 + in.material[c];
+      if (!is_regular(c)) continue;
+      const int32_t key = ((int32_t)in.regular[in.pattern[c]] << 16) | ((int32_t)in.level[c] << 8) | in.material[c];
       auto it = seen.find(key);
       if (it == seen.end()) {
         it = seen.emplace(key, (int32_t)out.scale_keys.size()).first;
@@ -98,7 +99,7 @@ bool build_owner_tiles(const TilingInput& in, int32_t tile_nodes, TilingOutput& 
     for (size_t j = 0; j < cells.size(); ++j) {
       const int32_t c = cells[j];
       uint32_t mask = 0;
-      if (in.p8 < 0 || in.pattern[c] != in.p8) {  // hanging-node cell: not staged in this tile
+      if (!is_regular(c)) {  // hanging-node cell: not staged in this tile
         r.pure8 = false;
         li_off[j + 1] = (int64_t)li_flat.size();
         continue;

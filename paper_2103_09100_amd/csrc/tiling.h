@@ -19,8 +19,9 @@ struct TilingInput {
   const uint8_t* material = nullptr;
   const int32_t* pattern_ndof = nullptr;
   const int64_t* pattern_koff = nullptr;
-  // regular 8-node cells: this pattern (identity orientation); the others are hanging-node cells
-  int32_t p8 = -1;
+  // regular 8-node cells (identity orientation): per pattern id, the index of the pattern's
+  // structured Walsh table (one per pattern library), -1 for hanging-node patterns; null: none
+  const int16_t* regular = nullptr;
   std::vector<int64_t> load_dof;       // internal dofs
   std::vector<double> load_val;
 };
@@ -36,8 +37,8 @@ struct TilingOutput {
   int64_t local_entries = 0;           // local nodes over all tiles
   std::vector<uint16_t> lidx;
   std::vector<LoadEntry> loads;
-  // scale classes of the pure 8-node tiles: key = level * 256 + material, in order of first use;
-  // an item of such a tile carries koff = kWalshC * class
+  // scale classes of the regular cells: key = (Walsh table << 16) | (level << 8) | material, in
+  // order of first use; an item of regular cells carries koff = kWalshC * class
   std::vector<int32_t> scale_keys;
 };
 

@@ -60,6 +60,24 @@ def build_library(nu, workers=0):
     return lib
 
 
+def combine(libs):
+    """One library of several Poisson ratios: pattern id = library index * 144 + pattern (each
+    Poisson ratio needs its own masters, Sec. 3.2.3; E and rho scale, nu does not)."""
+    K = [k for lib in libs for k in lib.K]
+    m = [v for lib in libs for v in lib.m]
+    om = np.concatenate([lib.omega for lib in libs])
+    masks = np.concatenate([lib.masks for lib in libs])
+    return Library(tuple(lib.nu for lib in libs), K, m, om, [k.shape[0] for k in K], masks)
+
+
+def material_libraries(mesh):
+    """Distinct Poisson ratios of the mesh's materials (sorted) and, per material, the index
+    of its library among them."""
+    nus = mesh.material_nu()
+    uniq = sorted(set(float(v) for v in nus))
+    return uniq, np.array([uniq.index(float(v)) for v in nus], dtype=np.int64)
+
+
 def canonicalise(mesh, seed=None):
     """Per-cell pattern id, orientation code and master-order node list.
 
@@ -110,4 +128,12 @@ def canonicalise(mesh, seed=None):
             perm = perms[int(k)]
             base = ptr[cells][:, None]
             out[base + np.arange(len(perm))[None, :]] = conn[base + perm[None, :]]
+    uniq, lib_of_mat = material_libraries(mesh)
+    if len(uniq) > 1:  # pattern ids of the combined library
+        pid = pid.astype(np.int64) + pt_count() * lib_of_mat[np.asarray(mesh.cell_mat, dtype=np.int64)]
     return pid.astype(np.uint16), code.astype(np.uint8), out
+
+
+def pt_count():
+    """Patterns per library (144)."""
+    return len(pt.table().master_mask)

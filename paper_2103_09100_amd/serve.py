@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import binding
-from .library import canonicalise
+from .library import canonicalise, material_libraries
 from .solver import device_patterns
 
 
@@ -63,7 +63,8 @@ class Server:
         self.clock = clock
 
     def _prepare(self, req):
-        pats = device_patterns(req.mesh.nu, self.setup_stream)
+        nus, _ = material_libraries(req.mesh)
+        pats = device_patterns(nus[0] if len(nus) == 1 else nus, self.setup_stream)
         pid, code, conn = req.canon if req.canon is not None else canonicalise(req.mesh)
         tn, bt, btm = self.shapes.shape(req.mesh) if self.shapes is not None else (0, 0, 0)
         desc, keep = binding.make_desc(req.mesh, pid, code, conn, dt=1.0, prod=self.prod, assembly="tiled",

@@ -9,16 +9,19 @@ given, and creates the device-resident state through the C ABI.
 import numpy as np
 
 from . import binding
-from .library import build_library, canonicalise
+from .library import build_library, canonicalise, combine, material_libraries
 
 _PATTERN_CACHE = {}
 
 
 def device_patterns(nu, stream=None, workers=0):
-    key = float(nu)
-    if key not in _PATTERN_CACHE:
-        _PATTERN_CACHE[key] = binding.Patterns(build_library(nu, workers=workers), stream)
-    return _PATTERN_CACHE[key]
+    """Device library for one Poisson ratio, or for several (a sequence: one library each,
+    pattern id = library index * 144 + pattern)."""
+    nus = tuple(float(v) for v in nu) if np.ndim(nu) else (float(nu),)
+    if nus not in _PATTERN_CACHE:
+        libs = [build_library(v, workers=workers) for v in nus]
+        _PATTERN_CACHE[nus] = binding.Patterns(libs[0] if len(libs) == 1 else combine(libs), stream)
+    return _PATTERN_CACHE[nus]
 
 
 class Simulation:
@@ -26,7 +29,8 @@ class Simulation:
                  u0=None, v0=None, stream=None, workers=0, tile_nodes=0, block_threads=0,
                  block_threads_mixed=0, graph_steps=0):
         self.mesh = mesh
-        self.patterns = device_patterns(mesh.nu, stream, workers)
+        nus, _ = material_libraries(mesh)
+        self.patterns = device_patterns(nus[0] if len(nus) == 1 else nus, stream, workers)
         pid, code, conn = canonicalise(mesh, seed=orient_seed)
         desc, keep = binding.make_desc(mesh, pid, code, conn, dt=1.0, prod=prod, state=state,
                                        assembly=assembly, u0=u0, v0=v0, tile_nodes=tile_nodes,
@@ -67,6 +71,14 @@ class Simulation:
 
     def write(self, u, um1, step):
         self.gpu.write(u, um1, step, self.stream)
+
+    def set_probes(self, dofs, capacity):
+        """Record u_{n+1} and the central-difference acceleration at these dofs from now on."""
+        self.gpu.set_probes(dofs, capacity, self.stream)
+
+    def read_probes(self):
+        """(u, a, first step) of the recorded probe rows."""
+        return self.gpu.read_probes(self.stream)
 
     def run(self, n_steps, snap_every=50):
         """Step to n_steps, reading u at every snap_every-th step and the last."""

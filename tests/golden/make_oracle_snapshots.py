@@ -25,9 +25,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-from meshgen import configs  # noqa: E402
-from oracle.solver import Oracle  # noqa: E402
-
 N_SAMPLE = 512
 
 
@@ -38,6 +35,8 @@ def main():
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--out", default=os.path.join(HERE, "cfg4_oracle_snapshots.txt"))
     args = ap.parse_args()
+    from meshgen import configs
+    from oracle.solver import Oracle  # the writer only: read() below parses the file alone
     t0 = time.time()
     mesh = configs.cfg4(n_steps=args.steps)
     o = Oracle(mesh, workers=args.workers)

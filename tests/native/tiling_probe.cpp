@@ -2,6 +2,7 @@
 // from Python and hands its output back, so that the index work of the tiling can be
 // checked exactly on the CPU.  Built by the test with g++ together with csrc/tiling.cpp.
 #include <cstring>
+#include <vector>
 
 #include "tiling.h"
 
@@ -28,7 +29,10 @@ int tiling_run(int64_t n_nodes, int64_t n_cells, const int64_t* cptr, const int3
   in.pattern = pattern;
   in.level = level;
   in.material = material;
-  in.p8 = p8;
+  static std::vector<int16_t> regular;
+  regular.assign(1 << 16, -1);
+  if (p8 >= 0) regular[p8] = 0;
+  in.regular = regular.data();
   in.load_dof.assign(load_dof, load_dof + n_load);
   in.load_val.assign(load_val, load_val + n_load);
   return sbfem::build_owner_tiles(in, tile_nodes, g_out) ? 1 : 0;

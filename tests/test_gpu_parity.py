@@ -326,3 +326,22 @@ def test_tile_shapes_agree(sim_mod, prod, shape):
     err = np.abs(s.u() - ref.u()).max() / np.abs(ref.u()).max()
     _say(f"  tile_nodes {lay['tile_nodes']}, max local {lay['max_local_nodes']}: {err:.3e}")
     assert err <= (1e-12 if prod == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prod,assembly,tol", [("fp64", "tiled", FP64_TOL), ("fp32", "tiled", FP32_TOL),
+                                                ("fp64", "atomic", FP64_TOL)])
+def test_two_poisson_ratio_libraries(sim_mod, prod, assembly, tol):
+    """Inclusions with their own Poisson ratio: two pattern libraries in one mesh (pattern id =
+    library * 144 + pattern, Sec. 3.2.3), each with its own regular-cell Walsh table, against the
+    oracle, which computes every cell with its material's Poisson ratio."""
+    m = configs.inclusion_mesh(seed=4, lcoarse=3, lfine=4, band=0.3, nu_incl=0.4)
+    configs._run_params(m, fm=2.0, n_steps=150)
+    assert (m.cell_mat == 1).any() and (m.cell_mat == 0).any()
+    ref = Oracle(m, workers=8).run(n_steps=150)
+    s = sim_mod.Simulation(m, prod=prod, assembly=assembly, orient_seed=7)
+    assert s.patterns.library.n_patterns == 288
+    assert abs(s.dt - ref["dt"]) <= 1e-14 * ref["dt"]
+    e = relative_error(s.run(150, 50), ref["snapshots"])
+    s.close()
+    _say(f"[two Poisson ratios, {m.n_dof} dofs, {prod} {assembly}] e_max {e:.3e}")
+    assert e <= tol

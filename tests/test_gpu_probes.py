@@ -1,0 +1,121 @@
+"""Probe time histories through the C ABI (sbfem_set_probes / sbfem_read_probes) against the
+oracle's histories: the displacement at a point (Sec. 5.2) and the central-difference
+acceleration (Sec. 5.3) recorded by the fused update of every step.
+
+Bounds: the displacement rows to the parity tolerance of the precision form (1e-9 with FP64
+products and state, 1e-5 for the mixed forms); the acceleration, a second difference of the
+displacement, to 4 tol max|u| / dt^2, and against the device's own displacement rows to the
+rounding of the stored state (4 eps_state max|u| / dt^2).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from meshgen import configs
+from oracle.solver import Oracle
+
+pytestmark = pytest.mark.gpu
+
+EPS_STATE = {"fp64": 2.0 ** -52, "kahan32": 2.0 ** -40, "fp32": 2.0 ** -23}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _mesh(name):
+    return configs.cfg1() if name == "cfg1" else configs.small_zoo(n_steps=200)
+
+
+def _probe_dofs(m, seed, count=48):
+    rng = np.random.default_rng(seed)
+    p = rng.choice(m.n_dof, count, replace=False)
+    p[7] = p[3]  # a repeated probe
+    fixed = np.flatnonzero(m.fixed.astype(bool))
+    if len(fixed):
+        p[11] = fixed[len(fixed) // 2]  # a fixed dof stays at zero
+    load = np.asarray(m.load_dof, dtype=np.int64)
+    if len(load):
+        p[0] = load[0]  # the loaded dof
+    return p
+
+
+_REF = {}
+
+
+def _oracle(name, n_steps, probes):
+    key = (name, n_steps, probes.tobytes())
+    if key not in _REF:
+        m = _mesh(name)
+        o = Oracle(m, workers=8)
+        _REF[key] = o.run(n_steps=n_steps, snap_every=0, energy=False, probes=probes)
+    return _REF[key]
+
+
+@pytest.mark.parametrize("name,prod,state,tol,graph", [
+    ("cfg1", "fp64", "fp64", 1e-9, 0), ("zoo", "fp64", "fp64", 1e-9, 0), ("zoo", "fp64", "fp64", 1e-9, 16),
+    ("zoo", "fp32", "fp32", 1e-5, 0), ("zoo", "fp32", "kahan32", 1e-5, 0)])
+def test_probe_histories_match_oracle(name, prod, state, tol, graph):
+    from paper_2103_09100_amd import solver
+    m = _mesh(name)
+    probes = _probe_dofs(m, 11)
+    n_steps = 200
+    _say(f"[probes {name} {prod}/{state} graph {graph}: {len(probes)} probes, {n_steps} steps]")
+    s = solver.Simulation(m, prod=prod, state=state, assembly="tiled", graph_steps=graph)
+    s.set_probes(probes, n_steps)
+    s.step(70)
+    s.step(n_steps - 70)
+    u, a, step0 = s.read_probes()
+    s.close()
+    ref = _oracle(name, n_steps, probes)
+    dt = ref["dt"]
+    assert step0 == 0 and u.shape == (n_steps, len(probes)) and a.shape == u.shape
+    umax = np.abs(ref["probe_u"]).max()
+    eu = np.abs(u - ref["probe_u"]).max() / umax
+    ea = np.abs(a - ref["probe_a"]).max() / (umax / dt ** 2)
+    # the device's acceleration against the second difference of its own displacement rows
+    own = (u[2:] - 2 * u[1:-1] + u[:-2]) / dt ** 2
+    es = np.abs(a[2:] - own).max() / (umax / dt ** 2)
+    _say(f"  u err {eu:.2e}, a err {ea:.2e} (of max|u|/dt^2), a vs own rows {es:.2e}")
+    assert eu <= tol
+    assert ea <= 4 * tol
+    assert es <= 8 * EPS_STATE[state]
+    assert np.all(u[:, 11] == 0.0) or not m.fixed.astype(bool).any()
+    assert np.array_equal(u[:, 7], u[:, 3]) and np.array_equal(a[:, 7], a[:, 3])
+
+
+def test_probe_capacity_rearm_and_removal():
+    from paper_2103_09100_amd import binding, solver
+    m = _mesh("zoo")
+    probes = _probe_dofs(m, 5, 20)
+    ref = _oracle("zoo", 60, probes)
+    s = solver.Simulation(m, prod="fp64", assembly="tiled")
+    s.set_probes(probes, 10)  # only the first 10 steps are kept
+    s.step(25)
+    u, a, step0 = s.read_probes()
+    assert step0 == 0 and u.shape == (10, len(probes))
+    scale = np.abs(ref["probe_u"]).max()
+    assert np.abs(u - ref["probe_u"][:10]).max() <= 1e-9 * scale
+    s.set_probes(probes[::-1].copy(), 50)  # re-armed at step 25, another order
+    s.step(35)
+    u, a, step0 = s.read_probes()
+    assert step0 == 25 and u.shape == (35, len(probes))
+    assert np.abs(u - ref["probe_u"][25:60, ::-1]).max() <= 1e-9 * scale
+    assert np.abs(a - ref["probe_a"][25:60, ::-1]).max() <= 4e-9 * scale / ref["dt"] ** 2
+    s.set_probes([], 0)
+    s.step(3)
+    u, a, step0 = s.read_probes()
+    assert u.shape[0] == 0
+    for bad in (dict(dofs=[m.n_dof], capacity=4), dict(dofs=[-1], capacity=4), dict(dofs=[0], capacity=-1)):
+        with pytest.raises(binding.SbfemError) as ei:
+            s.set_probes(**bad)
+        assert ei.value.status == binding.EINVAL
+    s.close()
+    s = solver.Simulation(m, prod="fp64", assembly="colour")
+    with pytest.raises(binding.SbfemError) as ei:
+        s.set_probes(probes, 4)
+    assert ei.value.status == binding.EINVAL
+    s.close()
