@@ -131,6 +131,22 @@ void sbfem_destroy_patterns(sbfem_patterns* p);
  */
 sbfem_status sbfem_mesh_footprint(const sbfem_patterns* p, const sbfem_mesh_desc* d, int64_t* bytes);
 
+/*
+ * The same host set-up split from the upload, for callers that admit a mesh by its
+ * footprint before creating it (a serving loop): sbfem_plan_mesh runs create_mesh's host
+ * set-up (validation, renumbering, tiling, mass; Alg. 1 initialisation) into a host plan and
+ * returns the device bytes sbfem_mesh_footprint would; sbfem_create_mesh_planned then makes
+ * the mesh from the plan without repeating it.  The plan keeps the pointers p and d: both
+ * must stay valid and unchanged until sbfem_create_mesh_planned returns.  A plan serves one
+ * create (SBFEM_EINVAL after that) and is freed by sbfem_destroy_plan, used or not.
+ * Errors: those of sbfem_create_mesh.
+ */
+typedef struct sbfem_plan sbfem_plan;
+sbfem_status sbfem_plan_mesh(sbfem_plan** out, const sbfem_patterns* p, const sbfem_mesh_desc* d,
+                             int64_t* device_bytes);
+sbfem_status sbfem_create_mesh_planned(sbfem_mesh** out, sbfem_plan* plan, void* hip_stream);
+void sbfem_destroy_plan(sbfem_plan* plan);
+
 /* Smallest element limit 2/omega_max,e over the cells (eqs. tcr, tcr_scale). */
 sbfem_status sbfem_critical_dt(const sbfem_patterns* p, const sbfem_mesh_desc* d, double* dt_cr);
 

@@ -34,7 +34,8 @@ STATE = {"fp64": 0, "fp32": 1, "kahan32": 2}
 ASM = {"atomic": 0, "colour": 1, "tiled": 2}
 LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
 
-EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint",
+EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint", "sbfem_plan_mesh",
+           "sbfem_create_mesh_planned", "sbfem_destroy_plan",
            "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n", "sbfem_set_graph_steps",
            "sbfem_step_batch", "sbfem_step_batch_noalloc", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
            "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_set_allocator", "sbfem_eigen_lowest",
@@ -67,6 +68,10 @@ _lib.sbfem_destroy_patterns.restype = None
 _lib.sbfem_mesh_footprint.argtypes = [_P, C.POINTER(MeshDesc), C.POINTER(C.c_int64)]
 _lib.sbfem_critical_dt.argtypes = [_P, C.POINTER(MeshDesc), C.POINTER(C.c_double)]
 _lib.sbfem_create_mesh.argtypes = [C.POINTER(_P), _P, C.POINTER(MeshDesc), _P]
+_lib.sbfem_plan_mesh.argtypes = [C.POINTER(_P), _P, C.POINTER(MeshDesc), C.POINTER(C.c_int64)]
+_lib.sbfem_create_mesh_planned.argtypes = [C.POINTER(_P), _P, _P]
+_lib.sbfem_destroy_plan.argtypes = [_P]
+_lib.sbfem_destroy_plan.restype = None
 _lib.sbfem_destroy_mesh.argtypes = [_P]
 _lib.sbfem_destroy_mesh.restype = None
 _lib.sbfem_step_n.argtypes = [_P, C.c_int64, _P]
@@ -206,12 +211,38 @@ def footprint(patterns, desc):
     return out.value
 
 
-class Mesh:
-    """A resident simulation (sbfem_mesh)."""
+class Plan:
+    """sbfem_plan_mesh: the host set-up of a mesh and its device footprint, kept until
+    Mesh(..., plan=) creates the mesh from it (the descriptor and its arrays stay referenced)."""
 
-    def __init__(self, patterns, desc, keep=None, stream=None):
+    def __init__(self, patterns, desc, keep=None):
+        h, b = _P(), C.c_int64()
+        _check(_lib.sbfem_plan_mesh(C.byref(h), patterns.handle, C.byref(desc), C.byref(b)))
+        self.handle, self.footprint = h, b.value
+        self.patterns, self.desc, self.keep = patterns, desc, keep
+
+    def close(self):
+        if self.handle:
+            _lib.sbfem_destroy_plan(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Mesh:
+    """A resident simulation (sbfem_mesh); with `plan` (a Plan of the same patterns and
+    descriptor) created by sbfem_create_mesh_planned without repeating the host set-up."""
+
+    def __init__(self, patterns, desc, keep=None, stream=None, plan=None):
         h = _P()
-        _check(_lib.sbfem_create_mesh(C.byref(h), patterns.handle, C.byref(desc), _stream(stream)))
+        if plan is not None:
+            try:
+                _check(_lib.sbfem_create_mesh_planned(C.byref(h), plan.handle, _stream(stream)))
+            finally:
+                plan.close()
+        else:
+            _check(_lib.sbfem_create_mesh(C.byref(h), patterns.handle, C.byref(desc), _stream(stream)))
         self.handle = h
         self.patterns = patterns
         self.n_dof = 3 * desc.n_nodes

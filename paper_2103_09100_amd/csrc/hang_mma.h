@@ -128,16 +128,14 @@ __device__ __forceinline__ double rot_sign(const HangRot& h) {
   return K == 0 ? h.sg0 : (K == 1 ? h.sg1 : h.sg2);
 }
 
-// the oriented (and, for reduced products, centred) displacement of dof j = 3 k + a of the
-// lane's cell, a taken from rotation slot K
+// the oriented (and, for reduced products, centred) displacement of a dof of the lane's cell
+// at node g, its component taken from rotation slot K
 template <int STATE, int K>
-__device__ __forceinline__ double hang_dof(const TiledArgs& a, gptr_t<int32_t> conn, int64_t conn0, int32_t count,
-                                           int c, int j, const HangRot& h) {
+__device__ __forceinline__ double hang_dof_at(const TiledArgs& a, int32_t g, const HangRot& h) {
   int src;
   double sg, r;
   rot_slot<K>(h, src, sg, r);
-  const int64_t g = conn[conn0 + (int64_t)(j / 3) * count + c];
-  return sg * state_load(a.u, STATE, a.ndof, 3 * g + src) - r;
+  return sg * state_load(a.u, STATE, a.ndof, 3 * (int64_t)g + src) - r;
 }
 
 template <int PREC, int STATE>
@@ -176,39 +174,63 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
   // output rows i = 16 rt + 4 p + v have component (p + rt + v) mod 3
   const HangRot ho = hang_rot<STATE, false>(a, p % 3, p0, p1, p2, s0, s1, s2, g0, live);
 
-  // stage K_p (rows and columns zero-padded to whole tiles): every thread first issues its
-  // loads of the row-major matrix (8 at a time, no wait in between), then writes LDS; the
-  // gathers below are in flight meanwhile
-  {
-    const int n = nd * nd;
-    const float inv_nd = 1.0f / (float)nd;
-    constexpr int kBatch = 8;
-    using GT = typename std::conditional<PREC == 0, double, float>::type;  // K32: FP32 or 16-bit-rounded
+  // Loads are issued in the order their results are needed, so that one memory round trip
+  // covers several of them (the counter of outstanding loads drains in order): the node ids
+  // of the lane's dofs, then K_p (every element the thread stages, into registers), then --
+  // once the ids are in -- the displacements; K_p goes to LDS while those are in flight.
+  const int n_k = nd * nd;
+  using GT = typename std::conditional<PREC == 0, double, float>::type;  // K32: FP32 or 16-bit-rounded
+  constexpr int kKMax = (kHangMaxDof * kHangMaxDof + 255) / 256;  // K elements per thread (24)
+  GT kv[kKMax];
+  auto load_k = [&]() {
     const gptr_t<GT> K = as_global(PREC == 0 ? (const GT*)(a.K64 + it.koff) : (const GT*)(a.K32 + it.koff));
-    for (int e0 = 0; e0 < n; e0 += 256 * kBatch) {
-      GT v[kBatch];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        const int e = e0 + b * 256 + tid;
-        v[b] = e < n ? K[e] : GT(0);
-      }
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        const int e = e0 + b * 256 + tid;
-        if (e < n) {
-          const int r = (int)(((float)e + 0.5f) * inv_nd);  // exact for e < 2^22
-          Kl[r * KP + (e - r * nd)] = (KT)v[b];
-        }
-      }
+    for (int b = 0; b < kKMax; ++b) {
+      const int e = b * 256 + tid;
+      kv[b] = e < n_k ? K[e] : GT(0);
     }
-    // zero padding: columns nd .. KP-1 of every row, and rows nd .. rows-1
+  };
+  const float inv_nd = 1.0f / (float)nd;
+  auto put_k = [&](int e, GT v) {
+    const int r = (int)(((float)e + 0.5f) * inv_nd);  // exact for e < 2^22
+    Kl[r * KP + (e - r * nd)] = (KT)v;
+  };
+  auto pad_k = [&]() {  // zero padding: columns nd .. KP-1 of every row, and rows nd .. rows-1
     const int padc = KP - nd;
     for (int e = tid; e < rows * padc; e += 256) {
       const int r = e / padc;
       Kl[r * KP + nd + (e - r * padc)] = KT(0);
     }
     for (int e = tid; e < (rows - nd) * nd; e += 256) Kl[(nd + e / nd) * KP + e % nd] = KT(0);
-  }
+  };
+  // K_p into LDS, rows and columns zero-padded to whole tiles
+  auto store_k = [&]() {
+#pragma unroll
+    for (int b = 0; b < kKMax; ++b) {
+      const int e = b * 256 + tid;
+      if (e < n_k) put_k(e, kv[b]);
+    }
+    pad_k();
+  };
+  // the same in batches of 8 elements per thread (fewer registers, one round trip per batch)
+  auto stage_k_batched = [&]() {
+    const gptr_t<GT> K = as_global(PREC == 0 ? (const GT*)(a.K64 + it.koff) : (const GT*)(a.K32 + it.koff));
+    constexpr int kBatch = 8;
+    for (int e0 = 0; e0 < n_k; e0 += 256 * kBatch) {
+      GT v[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int e = e0 + b * 256 + tid;
+        v[b] = e < n_k ? K[e] : GT(0);
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int e = e0 + b * 256 + tid;
+        if (e < n_k) put_k(e, v[b]);
+      }
+    }
+    pad_k();
+  };
 
   const gmut_t<RT> res = as_global_mut((RT*)a.hres) + it.res0 + c;
   if constexpr (PREC <= 1) {
@@ -220,12 +242,22 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
     // dofs j = 4 t + p have component (t + p) mod 3: the output rotation
     const HangRot hi = hang_rot<STATE, PREC != 0>(a, p % 3, p0, p1, p2, s0, s1, s2, g0, live);
     const int jmax = live ? nd : 0;
+    // FP64: K_p staged first (holding it in registers across the gathers would halve the
+    // blocks per CU)
+    if constexpr (PREC == 0) stage_k_batched();
+    int32_t gi[TMAX];
+    static_for<TMAX>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      const int j = 4 * t + p;
+      gi[t] = t < T && j < jmax ? conn[it.conn0 + (int64_t)(j / 3) * it.count + c] : -1;
+    });
+    if constexpr (PREC != 0) load_k();
     static_for<TMAX>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       b[t] = VT(0);
-      const int j = 4 * t + p;
-      if (t < T && j < jmax) b[t] = (VT)hang_dof<STATE, t % 3>(a, conn, it.conn0, it.count, c, j, hi);
+      if (gi[t] >= 0) b[t] = (VT)hang_dof_at<STATE, t % 3>(a, gi[t], hi);
     });
+    if constexpr (PREC != 0) store_k();
     __syncthreads();  // K staged
     using AT = typename std::conditional<PREC == 0, mma_d4, mma_f4>::type;
     AT acc[kHangRowTiles];
@@ -269,16 +301,26 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
     // dofs j = 32 t + 8 p + i have component (2 p + 2 t + i) mod 3
     const HangRot hi = hang_rot<STATE, true>(a, (2 * p) % 3, p0, p1, p2, s0, s1, s2, g0, live);
     const int jmax = live ? nd : 0;
+    int32_t gi[TMAX][8];
     static_for<TMAX>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       static_for<8>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const int j = 32 * t + 8 * p + i;
+        gi[t][i] = t < T && j < jmax ? conn[it.conn0 + (int64_t)(j / 3) * it.count + c] : -1;
+      });
+    });
+    load_k();
+    static_for<TMAX>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      static_for<8>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
         u[t][i] = 0.0f;
-        if (t < T && j < jmax) u[t][i] = (float)hang_dof<STATE, (2 * t + i) % 3>(a, conn, it.conn0, it.count, c, j, hi);
+        if (gi[t][i] >= 0) u[t][i] = (float)hang_dof_at<STATE, (2 * t + i) % 3>(a, gi[t][i], hi);
         mx = fmaxf(mx, fabsf(u[t][i]));
       });
     });
+    store_k();
     // FP16: a power of two per cell brings its largest value into [1, 2) (the cell's dofs are
     // spread over the lanes q, q + 16, q + 32, q + 48)
     float scale = 1.0f;

@@ -1150,13 +1150,9 @@ static sbfem_status internal_force(sbfem_mesh* m, hipStream_t s) {
   return SBFEM_OK;
 }
 
-sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const sbfem_mesh_desc* d,
-                               void* hip_stream) {
-  if (!out) return fail(SBFEM_EINVAL, "null output handle");
-  *out = nullptr;
-  MeshPlan P;
-  sbfem_status st = plan_mesh(p, d, P);
-  if (st != SBFEM_OK) return st;
+// The device mesh from its host plan (consumed: its tables move into the mesh or die here).
+static sbfem_status create_from_plan(sbfem_mesh** out, MeshPlan& P, const sbfem_patterns* p,
+                                     const sbfem_mesh_desc* d, void* hip_stream) {
   hipStream_t s = (hipStream_t)hip_stream;
   const int64_t ndof = P.ndof;
 
@@ -1298,6 +1294,56 @@ sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const 
   *out = m;
   return SBFEM_OK;
 }
+
+sbfem_status sbfem_create_mesh(sbfem_mesh** out, const sbfem_patterns* p, const sbfem_mesh_desc* d,
+                               void* hip_stream) {
+  if (!out) return fail(SBFEM_EINVAL, "null output handle");
+  *out = nullptr;
+  MeshPlan P;
+  sbfem_status st = plan_mesh(p, d, P);
+  if (st != SBFEM_OK) return st;
+  return create_from_plan(out, P, p, d, hip_stream);
+}
+
+// A host plan kept between sbfem_plan_mesh and sbfem_create_mesh_planned.
+struct sbfem_plan {
+  MeshPlan P;
+  const sbfem_patterns* p = nullptr;
+  const sbfem_mesh_desc* d = nullptr;
+  int64_t n_cells = 0, n_nodes = 0;
+  bool used = false;
+};
+
+sbfem_status sbfem_plan_mesh(sbfem_plan** out, const sbfem_patterns* p, const sbfem_mesh_desc* d,
+                             int64_t* device_bytes) {
+  if (!out) return fail(SBFEM_EINVAL, "null output handle");
+  *out = nullptr;
+  auto* pl = new sbfem_plan();
+  sbfem_status st = plan_mesh(p, d, pl->P);
+  if (st != SBFEM_OK) {
+    delete pl;
+    return st;
+  }
+  pl->p = p;
+  pl->d = d;
+  pl->n_cells = d->n_cells;
+  pl->n_nodes = d->n_nodes;
+  if (device_bytes) *device_bytes = plan_bytes(pl->P, d);
+  *out = pl;
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_create_mesh_planned(sbfem_mesh** out, sbfem_plan* plan, void* hip_stream) {
+  if (!out) return fail(SBFEM_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!plan || plan->used) return fail(SBFEM_EINVAL, "null or already used plan");
+  if (plan->d->n_cells != plan->n_cells || plan->d->n_nodes != plan->n_nodes)
+    return fail(SBFEM_EINVAL, "the descriptor changed since the plan was made");
+  plan->used = true;
+  return create_from_plan(out, plan->P, plan->p, plan->d, hip_stream);
+}
+
+void sbfem_destroy_plan(sbfem_plan* plan) { delete plan; }
 
 // Argument blocks of the owner-tile launches re-uploaded after a change of the mesh's buffers.
 static sbfem_status upload_tiled_args(sbfem_mesh* m, hipStream_t s) {

@@ -47,9 +47,10 @@ def link_cells(req):
 
 
 class Server:
-    """Admission in arrival order under a device-memory budget; host-side set-up
-    (linking cells, building tiles, uploading) runs on a worker thread and its
-    own stream so it overlaps the stepping of the admitted simulations."""
+    """Admission in arrival order under a device-memory budget; host-side set-up (linking
+    cells, building tiles: one host plan per request, which also gives its footprint) and
+    the uploads of admitted requests run on two worker threads, the uploads on their own
+    stream, so they overlap the stepping of the admitted simulations."""
 
     def __init__(self, budget_bytes=4 << 30, quantum=50, prod="fp32", stream=None, setup_stream=None,
                  clock=time.perf_counter, shapes=None, graph_steps=0):
@@ -71,7 +72,8 @@ class Server:
                                        tile_nodes=tn, block_threads=bt, block_threads_mixed=btm)
         dt_cr = binding.critical_dt(pats, desc)
         desc.dt = req.mesh.load.get("dt_factor", 0.5) * dt_cr
-        return pats, desc, keep, binding.footprint(pats, desc)
+        plan = binding.Plan(pats, desc, keep)  # host set-up once: footprint now, upload on admission
+        return pats, desc, keep, plan
 
     def run(self, requests, realtime=True):
         """Serve the requests; fills result, admitted and finished (seconds after start)."""
@@ -87,36 +89,39 @@ class Server:
         lock = threading.Lock()
         errors = []
 
-        def worker():
+        def prep_worker():   # host set-up in arrival order
             while True:
-                kind, r = None, None
-                try:
-                    kind, r = "create", to_create.get_nowait()
-                except q.Empty:
-                    try:
-                        kind, r = "prep", arrived.get(timeout=0.002)
-                    except q.Empty:
-                        continue
+                r = arrived.get()
                 if r is None:
                     return
                 try:
-                    if kind == "prep":
-                        r.extra["prep"] = self._prepare(r)
-                        with lock:
-                            prepared.append(r)
-                    else:
-                        pats, desc, keep, fp = r.extra.pop("prep")
-                        r.extra["gpu"] = binding.Mesh(pats, desc, keep, self.setup_stream)
-                        if self.graph_steps:
-                            r.extra["gpu"].set_graph_steps(self.graph_steps)
-                        with lock:
-                            created.append(r)
+                    r.extra["prep"] = self._prepare(r)
+                    with lock:
+                        prepared.append(r)
                 except Exception as exc:   # surfaced by the main loop
                     with lock:
                         errors.append(exc)
 
-        th = threading.Thread(target=worker, daemon=True)
-        th.start()
+        def create_worker():  # uploads of admitted requests on the set-up stream
+            while True:
+                r = to_create.get()
+                if r is None:
+                    return
+                try:
+                    pats, desc, keep, plan = r.extra.pop("prep")
+                    r.extra["gpu"] = binding.Mesh(pats, desc, keep, self.setup_stream, plan=plan)
+                    if self.graph_steps:
+                        r.extra["gpu"].set_graph_steps(self.graph_steps)
+                    with lock:
+                        created.append(r)
+                except Exception as exc:
+                    with lock:
+                        errors.append(exc)
+
+        threads = [threading.Thread(target=prep_worker, daemon=True),
+                   threading.Thread(target=create_worker, daemon=True)]
+        for th in threads:
+            th.start()
         active, used, i, n_done = [], 0, 0, 0
         try:
             while n_done < len(pending):
@@ -131,7 +136,7 @@ class Server:
                     # reserve budget in arrival order
                     while prepared:
                         r = prepared[0]
-                        fp = r.extra["prep"][3]
+                        fp = r.extra["prep"][3].footprint
                         if fp > self.budget:
                             raise binding.SbfemError(binding.ENOMEM,
                                                      f"request {r.rid} needs {fp} bytes, budget {self.budget}")
@@ -167,7 +172,8 @@ class Server:
         finally:
             to_create.put(None)
             arrived.put(None)
-            th.join(timeout=60)
+            for th in threads:
+                th.join(timeout=60)
         return requests
 
 

@@ -139,6 +139,47 @@ def test_footprint_equals_device_bytes(sim_mod):
     _say(f"[footprint] {len(meshes) * (len(cases) + 1)} meshes: footprint == device bytes")
 
 
+def test_planned_create_matches_direct(sim_mod):
+    """sbfem_plan_mesh + sbfem_create_mesh_planned: the plan's footprint is the footprint and
+    the device bytes, and the mesh steps exactly like one created directly (colour assembly:
+    bitwise; owner tiles: to the LDS summation order)."""
+    from paper_2103_09100_amd import binding
+    from paper_2103_09100_amd.library import canonicalise
+    m = configs.small_zoo()
+    for prod, asm, tol in (("fp64", "colour", 0.0), ("fp32", "tiled", 1e-12)):
+        direct = sim_mod.Simulation(m, prod=prod, assembly=asm)
+        pid, code, conn = canonicalise(m)
+        desc, keep = binding.make_desc(m, pid, code, conn, dt=direct.dt, prod=prod, assembly=asm)
+        plan = binding.Plan(direct.patterns, desc, keep)
+        assert plan.footprint == binding.footprint(direct.patterns, desc) == direct.gpu.info()["device_bytes"]
+        planned = binding.Mesh(direct.patterns, desc, keep, plan=plan)
+        assert plan.handle is None  # consumed and freed
+        assert planned.info()["device_bytes"] == plan.footprint
+        direct.step(150)
+        planned.step(150)
+        a, b = direct.u(), planned.read(0)[0]
+        err = float(np.abs(a - b).max() / np.abs(a).max())
+        _say(f"[planned create {prod} {asm}] max rel diff {err:.2e}")
+        assert err <= tol
+        planned.close()
+        direct.close()
+    # a plan serves one create; a null plan is rejected
+    import ctypes
+    s = sim_mod.Simulation(m, prod="fp32", assembly="tiled")
+    desc, keep = binding.make_desc(m, *canonicalise(m), dt=s.dt, prod="fp32", assembly="tiled")
+    lib = binding._lib
+    plan, nbytes = ctypes.c_void_p(), ctypes.c_int64()
+    assert lib.sbfem_plan_mesh(ctypes.byref(plan), s.patterns.handle, ctypes.byref(desc), ctypes.byref(nbytes)) == 0
+    first, second = ctypes.c_void_p(), ctypes.c_void_p()
+    assert lib.sbfem_create_mesh_planned(ctypes.byref(first), plan, None) == 0
+    assert lib.sbfem_create_mesh_planned(ctypes.byref(second), plan, None) == binding.EINVAL
+    assert not second.value
+    assert lib.sbfem_create_mesh_planned(ctypes.byref(second), None, None) == binding.EINVAL
+    lib.sbfem_destroy_plan(plan)
+    lib.sbfem_destroy_mesh(first)
+    s.close()
+
+
 @pytest.mark.parametrize("prod,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
 def test_served_requests_against_oracle(sim_mod, prod, tol):
     """Requests served in a mix (admitted under a memory budget, stepped in batched launches

@@ -119,3 +119,25 @@ def test_probe_capacity_rearm_and_removal():
         s.set_probes(probes, 4)
     assert ei.value.status == binding.EINVAL
     s.close()
+
+
+def test_probes_in_batched_steps():
+    """Probes of a mesh stepped in batched launches beside another mesh (sbfem_step_batch)."""
+    from paper_2103_09100_amd import binding, solver
+    m = _mesh("zoo")
+    probes = _probe_dofs(m, 21, 16)
+    ref = _oracle("zoo", 100, probes)
+    a = solver.Simulation(m, prod="fp64", assembly="tiled")
+    b = solver.Simulation(configs.cfg1(), prod="fp64", assembly="tiled")
+    a.set_probes(probes, 100)
+    for k in (30, 30, 40):
+        binding.step_batch([a.gpu, b.gpu], [k, k + 5])
+    u, acc, step0 = a.read_probes()
+    a.close()
+    b.close()
+    scale = np.abs(ref["probe_u"]).max()
+    err = np.abs(u - ref["probe_u"]).max() / scale
+    _say(f"[probes in batched steps] u err {err:.2e}")
+    assert step0 == 0 and u.shape == (100, len(probes))
+    assert err <= 1e-9
+    assert np.abs(acc - ref["probe_a"]).max() <= 4e-9 * scale / ref["dt"] ** 2
