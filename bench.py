@@ -63,7 +63,11 @@ def hang_kernel_name(prod, state="fp64"):
     return f"tiled_hang_mma<{PROD[prod]}, {STATE[state]}>"
 
 
-def roofline_block(r, copy_gbs, prod, state="fp64"):
+COUNTERS = {"cfg3": os.path.join(ROOT, "profiles", "cfg3_owner_tiles_hbm_counters.txt"),
+            "cfg4": os.path.join(ROOT, "profiles", "cfg4_pattern_rich_hbm_counters.txt")}
+
+
+def roofline_block(r, copy_gbs, prod, state="fp64", config="cfg3"):
     """Roofline of the owner-tile kernel (the dominant one) and of the whole step, from the
     library's algorithmic bytes per pass and the per-launch HIP events of the timed region."""
     k8 = r["kernels"]["element_8node"]
@@ -75,12 +79,15 @@ def roofline_block(r, copy_gbs, prod, state="fp64"):
     kname = owner_kernel_name(prod, state)
     return {"bound": "hbm", "kernel": f"{kname}: owner-tile pass (regular 8-node cells, hanging-cell row forces, update)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": counter_traffic(kname),
+            "traffic": counter_traffic(kname, COUNTERS.get(config, "")),
             "step_achieved": step_bytes / (r["ms_per_step"] * 1e-3) / 1e9,
             "step_frac": step_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
             "alg_bytes_per_launch": alg8, "alg_bytes_other_kernel": algo, "alg_bytes_per_step": step_bytes,
             "avg_launch_ms": k8["ms_avg"], "launches": k8["launches"],
+            "timing": "step time from a region with events around the whole region only; kernel durations "
+                      "from HIP events around each launch, on the launch stream, in a second region of as "
+                      "many steps",
             "hang_kernel": hang_kernel_name(prod, state), "hang_avg_launch_ms": kh["ms_avg"]}
 
 
@@ -161,7 +168,7 @@ def summarise_trace(trace_dir, out, header):
     print("\n".join(lines))
 
 
-def counter_traffic(kernel, path=os.path.join(ROOT, "profiles", "cfg3_owner_tiles_hbm_counters.txt")):
+def counter_traffic(kernel, path):
     """HBM bytes per dispatch of `kernel` from the committed counter summary, scaled by the copy
     kernel's factors; None if there is none or the kernel sources changed since it was taken."""
     if not os.path.exists(path):
@@ -193,24 +200,34 @@ def make_mesh(name):
     raise SystemExit(f"unknown config {name}")
 
 
-def time_mode(sim, torch, stream, steps, warmup):
-    """Wall time per step over `steps` steps (events around the whole region) and, from HIP
-    events the library records around each launch on the same stream in the same region,
-    the average duration of each kernel class."""
+def time_mode(sim, torch, stream, steps, warmup, instrumented=True):
+    """Wall time per step over `steps` steps, from events around the whole region only; then,
+    unless `instrumented` is false, the same number of steps again with HIP events that the
+    library records around each launch on the same stream (the per-launch events add a few
+    microseconds between launches, so the step time comes from the first region): the average
+    duration of each kernel class and the wall time per step of that second region."""
     with torch.cuda.stream(stream):
         sim.step(warmup)
         torch.cuda.synchronize()
-        sim.gpu.profile(True)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
         sim.step(steps)
         b.record(stream)
         torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        if not instrumented:
+            return ms, {}, None
+        sim.gpu.profile(True)
+        a.record(stream)
+        sim.step(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms_inst = a.elapsed_time(b) / steps
     prof = sim.gpu.profile_read()
     sim.gpu.profile(False)
     kernels = {k: dict(ms_total=v[0], launches=v[1], ms_avg=(v[0] / v[1] if v[1] else 0.0)) for k, v in prof.items()}
-    return a.elapsed_time(b) / steps, kernels
+    return ms, kernels, ms_inst
 
 
 def cpu_baseline(seconds=12.0, single_seconds=8.0):
@@ -378,7 +395,7 @@ def precision_sweep(torch, args):
     combos = [(p, st) for p in ("fp64", "fp32", "fp16", "bf16") for st in ("fp64", "kahan32", "fp32")]
     for prod, state in combos:
         sim = Simulation(mesh, prod=prod, state=state, stream=stream.cuda_stream)
-        ms, _ = time_mode(sim, torch, stream, args.sweep_time_steps, 5)
+        ms, _, _ = time_mode(sim, torch, stream, args.sweep_time_steps, 5, instrumented=False)
         sim.close()
         sim = Simulation(mesh, prod=prod, state=state, stream=stream.cuda_stream)
         snaps, H = {}, []
@@ -402,6 +419,10 @@ def precision_sweep(torch, args):
                    e_max_vs_fp64=num / den, energy_drift=drift, energy_samples=len(H))
         if golden is not None:
             row["e_max_vs_oracle_sampled"] = golden_error(golden, snaps)
+        if prod in ("fp16", "bf16"):
+            row["products_note"] = ("regular 8-node cells: Walsh operands and coefficients rounded to 16 bits, "
+                                    "FP32 arithmetic; hanging-node cells: 16-bit matrix instructions with FP32 "
+                                    "accumulation")
         rows.append(row)
         log(f"[sweep] {prod} products, {state} state: {ms:.3f} ms/step ({row['dof_steps_per_s']:.3e} DOF-steps/s), "
             f"e_max vs FP64 {row['e_max_vs_fp64']:.3e}, vs oracle (sampled) "
@@ -476,7 +497,7 @@ def cache_resident_mesh(torch, steps=500):
     finals = {}
     for prod in ("fp32", "fp64"):
         sim = Simulation(m, prod=prod, assembly="tiled", stream=stream.cuda_stream)
-        ms, _ = time_mode(sim, torch, stream, steps, 10)
+        ms, _, _ = time_mode(sim, torch, stream, steps, 10, instrumented=False)
         finals[prod] = sim.u()
         out[prod] = {"ms_per_step": ms, "dof_steps_per_s": m.n_dof / (ms * 1e-3)}
         sim.close()
@@ -520,10 +541,10 @@ def run_modes(torch, mesh, plan, stream, label="bench"):
         info = sim.gpu.info()
         log(f"[{label}] {mode}: created in {time.time() - t1:.0f} s, dt={sim.dt:.4e}, "
             f"{info['n_colours']} colours, {info['device_bytes'] / 1e9:.1f} GB, layout {sim.gpu.layout()}")
-        ms, prof = time_mode(sim, torch, stream, n_steps, n_warm)
+        ms, prof, ms_inst = time_mode(sim, torch, stream, n_steps, n_warm)
         finals[mode] = sim.u()
         results[mode] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), kernels=prof, steps=n_steps,
-                             layout=sim.gpu.layout())
+                             layout=sim.gpu.layout(), ms_per_step_instrumented=ms_inst)
         log(f"[{label}] {mode}: {ms:.3f} ms/step, {results[mode]['value']:.3e} DOF-steps/s, "
             + ", ".join(f"{k} {v['ms_avg']:.3f} ms x{v['launches']}" for k, v in prof.items()))
         sim.close()
@@ -547,7 +568,7 @@ def pattern_rich(torch, stream, copy_gbs, steps, warmup):
         prod = mode.split(":")[0]
         out[prod] = {"ms_per_step": r["ms_per_step"], "value": r["value"],
                      "kernels_ms_avg": {c: d["ms_avg"] for c, d in r["kernels"].items()},
-                     "roofline": roofline_block(r, copy_gbs, prod)}
+                     "roofline": roofline_block(r, copy_gbs, prod, config="cfg4")}
     out["speedup_fp32_vs_fp64"] = res["fp32:tiled"]["value"] / res["fp64:tiled"]["value"]
     ref = finals["fp64:tiled"]
     out["rel_err_fp32_vs_fp64"] = float(np.abs(finals["fp32:tiled"] - ref).max() / np.abs(ref).max())
@@ -652,7 +673,7 @@ def main():
     head = args.modes.split(",")[0]
     fp64 = next((m for m in args.modes.split(",") if m.startswith("fp64:")), None)
     r = results[head]
-    roof = roofline_block(r, copy_gbs, head.split(":")[0])
+    roof = roofline_block(r, copy_gbs, head.split(":")[0], config=args.config)
     if roof["alg_bytes_per_step"] != ab["step"]:
         log(f"[bench] warning: per-pass algorithmic bytes {roof['alg_bytes_per_step']} != step bytes {ab['step']}")
     out = {
@@ -673,6 +694,7 @@ def main():
                    "steps_per_call": args.steps},
         "roofline": roof,
         "modes": {k: dict(ms_per_step=v["ms_per_step"], value=v["value"], steps=v["steps"],
+                          ms_per_step_instrumented=v["ms_per_step_instrumented"],
                           kernels_ms_avg={c: d["ms_avg"] for c, d in v["kernels"].items()})
                   for k, v in results.items()},
     }
