@@ -55,8 +55,14 @@ typedef enum { SBFEM_STATE_FP64 = 0, SBFEM_STATE_FP32 = 1, SBFEM_STATE_KAHAN32 =
  *          whose row forces the owning blocks add (no atomics outside on-chip memory).
  */
 typedef enum { SBFEM_ASM_ATOMIC = 0, SBFEM_ASM_COLOUR = 1, SBFEM_ASM_TILED = 2 } sbfem_asm;
-/* Load-time function P(t) (Sec. 5, eqs. Ricker, Triangle, Lamb). */
-typedef enum { SBFEM_LOAD_RICKER = 0, SBFEM_LOAD_TRIANGLE = 1, SBFEM_LOAD_SINE_BURST = 2 } sbfem_load_kind;
+/* Load-time function P(t) (Sec. 5, eqs. Ricker, Triangle, Lamb), or a table of P(t_n) per step
+   (R_ext evaluated at t_n = n dt, Alg. 1). */
+typedef enum {
+  SBFEM_LOAD_RICKER = 0,
+  SBFEM_LOAD_TRIANGLE = 1,
+  SBFEM_LOAD_SINE_BURST = 2,
+  SBFEM_LOAD_TABLE = 3
+} sbfem_load_kind;
 
 typedef struct sbfem_patterns sbfem_patterns;  /* opaque: uploaded master-cell library */
 typedef struct sbfem_mesh sbfem_mesh;          /* opaque: one simulation's resident state */
@@ -105,6 +111,11 @@ typedef struct {
   int32_t tile_nodes;
   int32_t block_threads;
   int32_t block_threads_mixed;
+  /* SBFEM_LOAD_TABLE: P(t_n) = load_table[n] for 0 <= n < load_table_n, 0 from then on
+     (host [load_table_n], copied to the device by create_mesh; 8 B per entry in the
+     footprint).  Ignored by the other load kinds. */
+  int64_t load_table_n;
+  const double* load_table;
 } sbfem_mesh_desc;
 
 /*

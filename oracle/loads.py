@@ -29,8 +29,18 @@ def sine_burst(t, t1, n=5, P0=1.0):
     return np.where((t >= 0) & (t <= t1), val, 0.0)
 
 
+def table(t, P, dt):
+    """P(t_n) given per step (R_ext at t_n = n dt, Alg. 1): P[n] for 0 <= n < len(P), 0 after."""
+    P = np.asarray(P, dtype=np.float64)
+    n = np.floor(np.asarray(t, dtype=np.float64) / dt + 0.5).astype(np.int64)
+    inside = (n >= 0) & (n < len(P))
+    return np.where(inside, P[np.clip(n, 0, len(P) - 1)], 0.0)
+
+
 def evaluate(load, t):
     kind = load.get("kind", "ricker")
+    if kind == "table":
+        return table(t, load["P"], load["dt"])
     if kind == "ricker":
         return ricker(t, load["t1"], load.get("P0", 1.0))
     if kind == "triangle":

@@ -32,7 +32,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTCONV = 0, -1, -2, -3, -4, -5,
 PROD = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 STATE = {"fp64": 0, "fp32": 1, "kahan32": 2}
 ASM = {"atomic": 0, "colour": 1, "tiled": 2}
-LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2}
+LOAD_KIND = {"ricker": 0, "triangle": 1, "sine_burst": 2, "table": 3}
 
 EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footprint", "sbfem_plan_mesh",
            "sbfem_create_mesh_planned", "sbfem_destroy_plan",
@@ -58,6 +58,7 @@ class MeshDesc(C.Structure):
         ("prod", C.c_int32), ("state", C.c_int32), ("assembly", C.c_int32),
         ("u0", C.c_void_p), ("v0", C.c_void_p),
         ("tile_nodes", C.c_int32), ("block_threads", C.c_int32), ("block_threads_mixed", C.c_int32),
+        ("load_table_n", C.c_int64), ("load_table", C.c_void_p),
     ]
 
 
@@ -164,6 +165,8 @@ def make_desc(mesh, pid, orient, conn, dt, prod="fp64", state="fp64", assembly="
         load_val=np.ascontiguousarray(mesh.load_val, dtype=np.float64),
         u0=None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64),
         v0=None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64),
+        load_table=(np.ascontiguousarray(mesh.load["P"], dtype=np.float64)
+                    if mesh.load.get("kind") == "table" else None),
     )
     L = mesh.load
     d = MeshDesc()
@@ -193,6 +196,9 @@ def make_desc(mesh, pid, orient, conn, dt, prod="fp64", state="fp64", assembly="
     d.assembly = ASM[assembly]
     d.u0 = _ptr(keep["u0"])
     d.v0 = _ptr(keep["v0"])
+    if keep["load_table"] is not None:
+        d.load_table_n = len(keep["load_table"])
+        d.load_table = _ptr(keep["load_table"])
     d.tile_nodes = int(tile_nodes)
     d.block_threads = int(block_threads)
     d.block_threads_mixed = int(block_threads_mixed)

@@ -82,6 +82,37 @@ __device__ __forceinline__ double minv_load(const void* p, int32_t mode, int64_t
   return mode == 1 ? (double)as_global((const float*)p)[i] : as_global((const double*)p)[i];
 }
 
+// Streaming forms for data a pass touches once (u_{n-1}, the inverse mass, u_{n+1}, cell
+// records): non-temporal accesses, so that they do not displace from L2 the displacements that
+// neighbouring tiles read again.
+template <class T>
+__device__ __forceinline__ T ld_nt(gptr_t<T> p) {
+  return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void st_nt(gmut_t<T> p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+__device__ __forceinline__ double state_load_nt(const void* p, int32_t mode, int64_t ndof, int64_t i) {
+  if (mode == 0) return ld_nt(as_global((const double*)p) + i);
+  const gptr_t<float> q = as_global((const float*)p);
+  if (mode == 1) return (double)ld_nt(q + i);
+  return (double)ld_nt(q + i) + (double)ld_nt(q + ndof + i);
+}
+__device__ __forceinline__ void state_store_nt(void* p, int32_t mode, int64_t ndof, int64_t i, double v) {
+  if (mode == 0) {
+    st_nt(as_global_mut((double*)p) + i, v);
+    return;
+  }
+  const gmut_t<float> q = as_global_mut((float*)p);
+  const float hi = (float)v;
+  st_nt(q + i, hi);
+  if (mode == 2) st_nt(q + ndof + i, (float)(v - (double)hi));
+}
+__device__ __forceinline__ double minv_load_nt(const void* p, int32_t mode, int64_t i) {
+  return mode == 1 ? (double)ld_nt(as_global((const float*)p) + i) : ld_nt(as_global((const double*)p) + i);
+}
+
 // 16-bit product operands (values kept in FP32 registers; a product of two 16-bit values is
 // exact in FP32, so FMAs on them are 16-bit products with FP32 accumulation).
 __device__ __forceinline__ float round_fp16(float x) { return (float)(_Float16)x; }
@@ -127,6 +158,10 @@ __device__ __forceinline__ double load_time(const LoadParams& L, double t) {
   if (L.kind == 1) {  // triangle
     if (t < 0.0 || t > 2.0 * L.t1) return 0.0;
     return (1.0 - fabs(t / L.t1 - 1.0)) * L.P0;
+  }
+  if (L.kind == 3) {  // table of P(t_n): t is n dt up to rounding
+    const double n = floor(t / L.dt + 0.5);
+    return n >= 0.0 && n < (double)L.n_table ? as_global(L.table)[(int64_t)n] : 0.0;
   }
   // Hann-windowed sine burst
   if (t < 0.0 || t > L.t1) return 0.0;

@@ -14,6 +14,9 @@ struct LoadParams {
   int32_t cycles;
   double t1;
   double P0;
+  const double* table;  // kind 3: P(t_n) per step n (device), n < n_table
+  int64_t n_table;
+  double dt;            // kind 3: step of the table (t_n = n dt)
 };
 
 // Owner tile: a block updates the nodes [own0, own0 + n_own) (internal ids).

@@ -192,6 +192,7 @@ struct sbfem_mesh {
   void* u = nullptr;     // state storage per state_mode: FP64, FP32 or compensated FP32 pair
   void* um1 = nullptr;
   double* f = nullptr;
+  double* load_table = nullptr;  // P(t_n) per step (load kind TABLE)
   void* minv = nullptr;  // per dof: FP64, or FP32 with FP32 state
   double* matE = nullptr;
   int32_t* conn = nullptr;
@@ -280,7 +281,9 @@ sbfem_status validate_desc(const sbfem_patterns* p, const sbfem_mesh_desc* d) {
   if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(SBFEM_EINVAL, "dt must be > 0");
   if (d->load_nnz < 0 || (d->load_nnz > 0 && (!d->load_dof || !d->load_val)))
     return fail(SBFEM_EINVAL, "bad load vector");
-  if (d->load_kind < 0 || d->load_kind > 2) return fail(SBFEM_EINVAL, "unknown load kind");
+  if (d->load_kind < 0 || d->load_kind > 3) return fail(SBFEM_EINVAL, "unknown load kind");
+  if (d->load_kind == SBFEM_LOAD_TABLE && (d->load_table_n < 1 || !d->load_table))
+    return fail(SBFEM_EINVAL, "a load table needs at least one entry");
   if (d->prod < SBFEM_PROD_FP64 || d->prod > SBFEM_PROD_BF16)
     return fail(SBFEM_EINVAL, "unknown product precision %d", d->prod);
   if (d->state < SBFEM_STATE_FP64 || d->state > SBFEM_STATE_KAHAN32)
@@ -351,6 +354,7 @@ void for_each_buffer(const MeshPlan& P, const sbfem_mesh_desc* d, sbfem_mesh* m,
   if (P.force_array) f(slot(&sbfem_mesh::f), (size_t)(ndof * 8));
   f(slot(&sbfem_mesh::matE), 256 * 8);
   f(slot(&sbfem_mesh::flag_d), sizeof(unsigned long long));
+  if (d->load_kind == SBFEM_LOAD_TABLE) f(slot(&sbfem_mesh::load_table), (size_t)d->load_table_n * 8);
   if (d->assembly == SBFEM_ASM_TILED) {
     const auto& to = P.to;
     f(slot(&sbfem_mesh::otiles), to.tiles.size() * sizeof(sbfem::OwnerTile));
@@ -1024,6 +1028,7 @@ void sbfem_destroy_mesh(sbfem_mesh* m) {
   dfree(m->alloc, m->hres);
   dfree(m->alloc, m->dWs64);
   dfree(m->alloc, m->dWs32);
+  dfree(m->alloc, m->load_table);
   dfree(m->alloc, m->probe_ptr);
   dfree(m->alloc, m->probes);
   dfree(m->alloc, m->probe_u);
@@ -1173,6 +1178,7 @@ static sbfem_status create_from_plan(sbfem_mesh** out, MeshPlan& P, const sbfem_
   m->L.cycles = d->load_cycles;
   m->L.t1 = d->load_t1;
   m->L.P0 = d->load_P0;
+  m->L.dt = d->dt;
   m->nnz = (int64_t)P.bidx.size();
   m->n_colours = P.n_colours;
   m->groups = P.groups;
@@ -1231,6 +1237,11 @@ static sbfem_status create_from_plan(sbfem_mesh** out, MeshPlan& P, const sbfem_
     H2D(m->minv, P.minv.data(), ndof * 8);
   }
   H2D(m->matE, P.matE.data(), 256 * 8);
+  if (d->load_kind == SBFEM_LOAD_TABLE) {
+    H2D(m->load_table, d->load_table, (size_t)d->load_table_n * 8);
+    m->L.table = m->load_table;
+    m->L.n_table = d->load_table_n;
+  }
   const unsigned long long no_flag = ~0ull;
   H2D(m->flag_d, &no_flag, sizeof(no_flag));
   if (e == hipSuccess && m->f) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
@@ -1271,7 +1282,7 @@ static sbfem_status create_from_plan(sbfem_mesh** out, MeshPlan& P, const sbfem_
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = sbfem::launch_fill(m->f, ndof, 0.0, s);
   }
-  const double P0t = load_time_host(m->L, 0.0);
+  const double P0t = d->load_kind == SBFEM_LOAD_TABLE ? d->load_table[0] : load_time_host(m->L, 0.0);
   std::vector<double> um1(ndof);
   std::vector<double> fext(ndof, 0.0);
   for (size_t i = 0; i < P.bidx.size(); ++i) fext[P.bidx[i]] = P0t * P.bval[i];
@@ -1886,6 +1897,7 @@ extern "C" sbfem_status sbfem_set_probes(sbfem_mesh* m, int32_t n_probes, const 
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t s = (hipStream_t)hip_stream;
   HIP_TRY(hipStreamSynchronize(s));  // launches in flight may still read the old buffers
+  dfree(m->alloc, m->load_table);
   dfree(m->alloc, m->probe_ptr);
   dfree(m->alloc, m->probes);
   dfree(m->alloc, m->probe_u);

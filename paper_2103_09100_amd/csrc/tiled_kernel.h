@@ -152,7 +152,9 @@ __device__ __forceinline__ void walsh8_sym(cptr_t<T> C, const T (&ue)[24], T (&f
 
 // the lane's 16-byte record of local node indices in a regular-cell item
 __device__ __forceinline__ uint4 cell8_record(const TiledArgs& a, const CellItem& it, int lane) {
-  return load_global(as_global(reinterpret_cast<const uint4*>(a.lidx)) + ((it.lidx0 >> 3) + lane));
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = ld_nt(as_global(reinterpret_cast<const u32x4*>(a.lidx)) + ((it.lidx0 >> 3) + lane));
+  return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 // Precision forms of the hanging-cell pass with one lane per cell: kernels instantiated with
@@ -575,8 +577,8 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
       pu[j] = pp[j] = pm[j] = 0.0;
       if (i < n_dof) {
         if constexpr (FP32) pu[j] = state_load(a.u, STATE, a.ndof, d0 + i);
-        pp[j] = state_load(a.um1, STATE, a.ndof, d0 + i);
-        pm[j] = minv_load(a.minv, STATE, d0 + i);
+        pp[j] = state_load_nt(a.um1, STATE, a.ndof, d0 + i);
+        pm[j] = minv_load_nt(a.minv, STATE, d0 + i);
       }
     }
   }
@@ -622,7 +624,7 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
       if (i < n_dof) {
         const double un = FP32 ? pu[j] : (double)ul[i];
         const double v = (a.dt2 * pm[j] * (-fl[i]) + 2.0 * un - cm * pp[j]) * inv;
-        state_store(a.um1, STATE, a.ndof, d0 + i, v);
+        state_store_nt(a.um1, STATE, a.ndof, d0 + i, v);
         ok &= state_finite(STATE, v);
         if (a.n_probes) {  // uniform
           const int32_t e0 = a.probe_ptr[ti], e1 = a.probe_ptr[ti + 1];

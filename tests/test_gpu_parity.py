@@ -345,3 +345,25 @@ def test_two_poisson_ratio_libraries(sim_mod, prod, assembly, tol):
     s.close()
     _say(f"[two Poisson ratios, {m.n_dof} dofs, {prod} {assembly}] e_max {e:.3e}")
     assert e <= tol
+
+
+@pytest.mark.parametrize("prod,assembly,tol", [("fp64", "tiled", FP64_TOL), ("fp32", "tiled", FP32_TOL),
+                                                ("fp64", "atomic", FP64_TOL)])
+def test_table_load(sim_mod, prod, assembly, tol):
+    """P(t_n) given per step (load kind TABLE), a seeded table shorter than the run, on the
+    all-pattern mesh, against the oracle's table load; the table is part of the footprint."""
+    m = configs.small_zoo(n_steps=160)
+    o = Oracle(m, workers=8)
+    dt = m.load["dt_factor"] * o.critical_dt()
+    rng = np.random.default_rng(23)
+    t = np.arange(120) * dt
+    P = np.sin(2 * np.pi * t / (40 * dt)) * np.exp(-t / (60 * dt)) + 0.1 * rng.normal(size=120)
+    m.load = dict(m.load, kind="table", P=P, dt=dt)
+    ref = Oracle(m, workers=8).run(n_steps=160, dt=dt, snap_every=40, energy=False)
+    s = sim_mod.Simulation(m, prod=prod, assembly=assembly)
+    assert abs(s.dt - dt) <= 1e-14 * dt
+    assert s.gpu.info()["device_bytes"] == s.footprint
+    e = relative_error(s.run(160, 40), ref["snapshots"])
+    s.close()
+    _say(f"[table load {prod} {assembly}] e_max = {e:.3e}")
+    assert e <= tol
