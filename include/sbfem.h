@@ -185,6 +185,15 @@ void sbfem_destroy_mesh(sbfem_mesh* m);
 sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream);
 
 /*
+ * With steps > 0, step_n launches its steps in chunks of `steps` and, after each chunk, waits
+ * for it and examines the non-finite record: a chunk that produced a non-finite u_{n+1} makes
+ * that step_n return SBFEM_EUNSTABLE at once (the mesh's step is then the end of that chunk,
+ * no further chunk is launched).  The call then blocks once per chunk; steps = 0 (the
+ * default) restores the asynchronous behaviour above.  Errors: SBFEM_EINVAL (steps < 0).
+ */
+sbfem_status sbfem_set_check_interval(sbfem_mesh* m, int64_t steps);
+
+/*
  * Advance several meshes in one stream: mesh i takes n_steps[i] steps (a mesh
  * may appear once; n_steps[i] >= 0).  Owner-tile meshes that share a pattern
  * library, product precision, state storage and block shape advance together:

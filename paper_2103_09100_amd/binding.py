@@ -39,7 +39,7 @@ EXPORTS = ["sbfem_upload_patterns", "sbfem_destroy_patterns", "sbfem_mesh_footpr
            "sbfem_critical_dt", "sbfem_create_mesh", "sbfem_destroy_mesh", "sbfem_step_n", "sbfem_set_graph_steps",
            "sbfem_step_batch", "sbfem_step_batch_noalloc", "sbfem_read_state", "sbfem_write_state", "sbfem_mesh_info",
            "sbfem_profile", "sbfem_profile_read", "sbfem_mesh_layout", "sbfem_set_allocator", "sbfem_eigen_lowest",
-           "sbfem_set_probes", "sbfem_read_probes",
+           "sbfem_set_probes", "sbfem_read_probes", "sbfem_set_check_interval",
            "sbfem_last_error"]
 KERNEL_CLASSES = ("load", "element_8node", "element_larger", "update")
 
@@ -88,6 +88,7 @@ _lib.sbfem_mesh_layout.argtypes = [_P, _P, C.c_int32]
 _lib.sbfem_eigen_lowest.argtypes = [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, _P, _P,
                                      C.POINTER(C.c_int32), _P]
 _lib.sbfem_set_probes.argtypes = [_P, C.c_int32, _P, C.c_int64, _P]
+_lib.sbfem_set_check_interval.argtypes = [_P, C.c_int64]
 _lib.sbfem_read_probes.argtypes = [_P, _P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _P]
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -293,6 +294,10 @@ class Mesh:
         n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
         _check(_lib.sbfem_profile_read(self.handle, ms.ctypes.data, n.ctypes.data))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def set_check_interval(self, steps):
+        """sbfem_set_check_interval: step_n examines the non-finite record every `steps` steps."""
+        _check(_lib.sbfem_set_check_interval(self.handle, int(steps)))
 
     def set_probes(self, dofs, capacity, stream=None):
         """sbfem_set_probes: record u_{n+1} and the acceleration of step n at these dofs."""

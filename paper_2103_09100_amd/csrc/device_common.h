@@ -93,21 +93,20 @@ template <class T>
 __device__ __forceinline__ void st_nt(gmut_t<T> p, T v) {
   __builtin_nontemporal_store(v, p);
 }
+// (the compensated pair keeps ordinary accesses: its two halves streamed separately were slower)
 __device__ __forceinline__ double state_load_nt(const void* p, int32_t mode, int64_t ndof, int64_t i) {
   if (mode == 0) return ld_nt(as_global((const double*)p) + i);
-  const gptr_t<float> q = as_global((const float*)p);
-  if (mode == 1) return (double)ld_nt(q + i);
-  return (double)ld_nt(q + i) + (double)ld_nt(q + ndof + i);
+  if (mode == 1) return (double)ld_nt(as_global((const float*)p) + i);
+  return state_load(p, mode, ndof, i);
 }
 __device__ __forceinline__ void state_store_nt(void* p, int32_t mode, int64_t ndof, int64_t i, double v) {
   if (mode == 0) {
     st_nt(as_global_mut((double*)p) + i, v);
-    return;
+  } else if (mode == 1) {
+    st_nt(as_global_mut((float*)p) + i, (float)v);
+  } else {
+    state_store(p, mode, ndof, i, v);
   }
-  const gmut_t<float> q = as_global_mut((float*)p);
-  const float hi = (float)v;
-  st_nt(q + i, hi);
-  if (mode == 2) st_nt(q + ndof + i, (float)(v - (double)hi));
 }
 __device__ __forceinline__ double minv_load_nt(const void* p, int32_t mode, int64_t i) {
   return mode == 1 ? (double)ld_nt(as_global((const float*)p) + i) : ld_nt(as_global((const double*)p) + i);

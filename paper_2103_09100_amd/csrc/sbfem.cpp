@@ -207,6 +207,7 @@ struct sbfem_mesh {
   unsigned long long* flag_h = nullptr;  // its copy in pinned host memory
   hipEvent_t flag_ev = nullptr;
   bool flag_pending = false;
+  int64_t check_every = 0;  // step_n: examine the record every this many steps (0: next call)
   std::vector<sbfem::TileRange> groups;  // one per colour
   // kernel timing
   bool profiling = false;
@@ -1490,6 +1491,18 @@ sbfem_status sbfem_set_graph_steps(sbfem_mesh* m, int32_t steps) {
   return SBFEM_OK;
 }
 
+// n steps launched (graph chunks first, then one by one), the non-finite record copied behind them
+static sbfem_status launch_steps(sbfem_mesh* m, int64_t n, hipStream_t s) {
+  int64_t left = n;
+  sbfem_status st = graph_steps_single(m, left, s);
+  if (st != SBFEM_OK) return st;
+  for (int64_t k = 0; k < left; ++k) {
+    st = enqueue_step(m, s);
+    if (st != SBFEM_OK) return st;
+  }
+  return n > 0 ? finish_steps(m, s) : SBFEM_OK;
+}
+
 sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream) {
   if (!m) return fail(SBFEM_EINVAL, "null mesh");
   if (n_steps < 0) return fail(SBFEM_EINVAL, "negative step count");
@@ -1497,14 +1510,24 @@ sbfem_status sbfem_step_n(sbfem_mesh* m, int64_t n_steps, void* hip_stream) {
   sbfem_status st = check_flag(m);
   if (st != SBFEM_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
-  int64_t left = n_steps;
-  st = graph_steps_single(m, left, s);
-  if (st != SBFEM_OK) return st;
-  for (int64_t k = 0; k < left; ++k) {
-    st = enqueue_step(m, s);
+  if (m->check_every <= 0) return launch_steps(m, n_steps, s);
+  // chunks of check_every steps, each examined before the next is launched
+  for (int64_t left = n_steps; left > 0;) {
+    const int64_t k = std::min(left, m->check_every);
+    st = launch_steps(m, k, s);
+    if (st != SBFEM_OK) return st;
+    left -= k;
+    HIP_TRY(hipEventSynchronize(m->flag_ev));
+    st = check_flag(m);
     if (st != SBFEM_OK) return st;
   }
-  if (n_steps > 0) return finish_steps(m, s);
+  return SBFEM_OK;
+}
+
+sbfem_status sbfem_set_check_interval(sbfem_mesh* m, int64_t steps) {
+  if (!m) return fail(SBFEM_EINVAL, "null mesh");
+  if (steps < 0) return fail(SBFEM_EINVAL, "negative check interval");
+  m->check_every = steps;
   return SBFEM_OK;
 }
 
@@ -1897,7 +1920,6 @@ extern "C" sbfem_status sbfem_set_probes(sbfem_mesh* m, int32_t n_probes, const 
   HIP_TRY(hipSetDevice(m->device));
   hipStream_t s = (hipStream_t)hip_stream;
   HIP_TRY(hipStreamSynchronize(s));  // launches in flight may still read the old buffers
-  dfree(m->alloc, m->load_table);
   dfree(m->alloc, m->probe_ptr);
   dfree(m->alloc, m->probes);
   dfree(m->alloc, m->probe_u);

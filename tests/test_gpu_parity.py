@@ -176,6 +176,33 @@ def test_unstable_step_reported(sim_mod):
     assert ei.value.status == binding.EUNSTABLE
 
 
+def test_unstable_step_reported_within_the_call(sim_mod):
+    """With a check interval, the step_n call that produces the non-finite state reports it,
+    stops at the end of that chunk and launches nothing more."""
+    from paper_2103_09100_amd import binding
+    m = configs.cfg1()
+    s = sim_mod.Simulation(m)
+    s2 = sim_mod.Simulation(m, dt=3.0 * s.dt_cr)
+    s2.gpu.set_check_interval(50)
+    with pytest.raises(binding.SbfemError) as ei:
+        s2.step(100000)
+    assert ei.value.status == binding.EUNSTABLE
+    u, step = s2.gpu.read(0)  # the record was reported once; the state is that of the chunk's end
+    _say(f"[unstable, check every 50 steps] stopped at step {step}")
+    assert 0 < step < 100000 and step % 50 == 0
+    assert not np.isfinite(u).all()
+    # a stable mesh with the same interval steps exactly like one without
+    a = sim_mod.Simulation(m, assembly="colour")
+    b = sim_mod.Simulation(m, assembly="colour")
+    b.gpu.set_check_interval(7)
+    a.step(300)
+    b.step(300)
+    assert np.array_equal(a.u(), b.u())
+    with pytest.raises(binding.SbfemError) as ei:
+        b.gpu.set_check_interval(-1)
+    assert ei.value.status == binding.EINVAL
+
+
 def test_invalid_mesh_rejected(sim_mod):
     from paper_2103_09100_amd import binding, library
     m = configs.cfg1()

@@ -141,3 +141,25 @@ def test_probes_in_batched_steps():
     assert step0 == 0 and u.shape == (100, len(probes))
     assert err <= 1e-9
     assert np.abs(acc - ref["probe_a"]).max() <= 4e-9 * scale / ref["dt"] ** 2
+
+
+def test_probes_keep_the_meshs_other_buffers():
+    """Setting probes on a mesh with a load table leaves the table in place: the run still
+    matches the oracle."""
+    from paper_2103_09100_amd import solver
+    m = _mesh("zoo")
+    o = Oracle(m, workers=8)
+    dt = m.load["dt_factor"] * o.critical_dt()
+    P = np.sin(np.arange(90) * 0.2)
+    m.load = dict(m.load, kind="table", P=P, dt=dt)
+    probes = _probe_dofs(m, 31, 12)
+    ref = Oracle(m, workers=8).run(n_steps=100, dt=dt, snap_every=0, energy=False, probes=probes)
+    s = solver.Simulation(m, prod="fp64", assembly="tiled")
+    s.set_probes(probes, 100)
+    s.step(100)
+    u, a, step0 = s.read_probes()
+    s.close()
+    scale = np.abs(ref["probe_u"]).max()
+    err = np.abs(u - ref["probe_u"]).max() / scale
+    _say(f"[probes with a load table] u err {err:.2e}")
+    assert err <= 1e-9
