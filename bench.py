@@ -485,6 +485,44 @@ def small_mesh_latency(torch, steps=1000, graph_steps=50, prods=("fp64", "fp32")
     return out
 
 
+def eigen_workload(torch, levels=(1, 2), k=100):
+    """Sec. 5.1: the lowest k circular frequencies of the sliding cube (edge 8, E = 1000,
+    nu = 0.3, rho = 1) by sbfem_eigen_lowest on the element-by-element operator; wall time of
+    the call and the error against the analytic 3D frequencies (P and S waves with the
+    paper's multiplicity rule)."""
+    from meshgen import configs
+    from paper_2103_09100_amd.solver import Simulation
+    L, E, NU, RHO = 8.0, 1000.0, 0.3, 1.0
+    vp = np.sqrt(E * (1 - NU) / (RHO * (1 + NU) * (1 - 2 * NU)))
+    vs = np.sqrt(E / (2 * RHO * (1 + NU)))
+    exact = []
+    for i in range(12):
+        for j in range(12):
+            for l in range(12):
+                if i == j == l == 0:
+                    continue
+                kk = np.pi * np.sqrt(i * i + j * j + l * l) / L
+                zeros = (i == 0) + (j == 0) + (l == 0)
+                exact += [vp * kk] + [vs * kk] * {2: 0, 1: 1, 0: 2}[zeros]
+    exact = np.sort(exact)[:k]
+    out = {"workload": f"Sec. 5.1 sliding cube, lowest {k} frequencies, FP64", "levels": []}
+    for level in levels:
+        m = configs.sliding_cube(level, L=L, E=E, rho=RHO, nu=NU)
+        sim = Simulation(m, prod="fp64", state="fp64", assembly="tiled")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, r, it = sim.gpu.eigen_lowest(k, max_iter=400, tol=1e-9)
+        dt = time.perf_counter() - t0
+        sim.close()
+        err = float(np.sqrt(((w - exact) ** 2).sum() / (exact ** 2).sum()))
+        row = {"level": level, "n_dof": m.n_dof, "seconds": dt, "iterations": it, "max_residual": float(r.max()),
+               "omega_1": float(w[0]), "omega_k": float(w[-1]), "rel_error_vs_analytic": err}
+        out["levels"].append(row)
+        log(f"[eigen] cube level {level} ({m.n_dof} dofs): {k} frequencies in {dt:.2f} s, {it} iterations, "
+            f"residual {r.max():.1e}, error vs analytic {err:.4f}")
+    return out
+
+
 def cache_resident_mesh(torch, steps=500):
     """The 2e6-dof all-pattern mesh (it fits the 256 MB last-level cache): time per step and
     DOF-steps/s of the FP32 and FP64 paths, with their final states compared."""
@@ -589,6 +627,8 @@ def main():
     ap.add_argument("--serve", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--small", type=int, default=1000, help="steps of the small-mesh latency check (0: skip)")
     ap.add_argument("--mid", type=int, default=500, help="steps of the cache-resident 2e6-dof mesh (0: skip)")
+    ap.add_argument("--eigen-level", type=int, default=2,
+                    help="finest refinement of the Sec. 5.1 eigenfrequency cube (-1: skip)")
     ap.add_argument("--pattern-rich-steps", type=int, default=200,
                     help="steps of the 2e7-dof all-pattern mesh, with its own roofline (0: skip)")
     ap.add_argument("--accuracy-steps", type=int, default=0,
@@ -709,6 +749,9 @@ def main():
         out["small_mesh_step_us"] = small_mesh_latency(torch, args.small, args.graph_steps)
     if args.mid > 0:
         out["cache_resident_mesh"] = cache_resident_mesh(torch, args.mid)
+    if args.eigen_level >= 0:
+        out["eigen_workload"] = eigen_workload(torch, levels=tuple(range(max(0, args.eigen_level - 1),
+                                                                         args.eigen_level + 1)))
     if args.serve > 0:
         out["serving"] = serving(torch, args)
         out["p99_latency_s"] = out["serving"]["budget"]["p99_s"]

@@ -93,7 +93,7 @@ template <class T>
 __device__ __forceinline__ void st_nt(gmut_t<T> p, T v) {
   __builtin_nontemporal_store(v, p);
 }
-// (the compensated pair keeps ordinary accesses: its two halves streamed separately were slower)
+// (the compensated pair, two FP32 arrays per value, keeps ordinary accesses)
 __device__ __forceinline__ double state_load_nt(const void* p, int32_t mode, int64_t ndof, int64_t i) {
   if (mode == 0) return ld_nt(as_global((const double*)p) + i);
   if (mode == 1) return (double)ld_nt(as_global((const float*)p) + i);
