@@ -394,3 +394,39 @@ def test_table_load(sim_mod, prod, assembly, tol):
     s.close()
     _say(f"[table load {prod} {assembly}] e_max = {e:.3e}")
     assert e <= tol
+
+
+def test_degenerate_inputs(sim_mod):
+    """An empty mesh, a non-positive time step and an empty load table are refused; zero steps
+    change nothing; a mesh whose dofs are all fixed stays at rest under load."""
+    from paper_2103_09100_amd import binding, library
+    m = configs.cfg1()
+    pats = sim_mod.device_patterns(m.nu)
+    pid, code, conn = library.canonicalise(m)
+    d, keep = binding.make_desc(m, pid, code, conn, dt=0.01, assembly="tiled")
+    d.n_cells = 0
+    with pytest.raises(binding.SbfemError) as ei:
+        binding.Mesh(pats, d, keep)
+    assert ei.value.status == binding.EINVAL
+    for dt in (0.0, -1.0, float("nan")):
+        d, keep = binding.make_desc(m, pid, code, conn, dt=dt, assembly="tiled")
+        with pytest.raises(binding.SbfemError) as ei:
+            binding.Mesh(pats, d, keep)
+        assert ei.value.status == binding.EINVAL
+    d, keep = binding.make_desc(m, pid, code, conn, dt=0.01, assembly="tiled")
+    d.load_kind = 3  # a table without entries
+    with pytest.raises(binding.SbfemError) as ei:
+        binding.Mesh(pats, d, keep)
+    assert ei.value.status == binding.EINVAL
+    s = sim_mod.Simulation(m)
+    s.step(10)
+    u, um1, n = s.state()
+    s.step(0)
+    u2, um12, n2 = s.state()
+    assert n2 == n == 10 and np.array_equal(u, u2) and np.array_equal(um1, um12)
+    s.close()
+    m.fixed = np.ones_like(m.fixed)
+    s = sim_mod.Simulation(m)
+    s.step(50)
+    assert not s.u().any()
+    s.close()
