@@ -174,22 +174,11 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
   // output rows i = 16 rt + 4 p + v have component (p + rt + v) mod 3
   const HangRot ho = hang_rot<STATE, false>(a, p % 3, p0, p1, p2, s0, s1, s2, g0, live);
 
-  // Loads are issued in the order their results are needed, so that one memory round trip
-  // covers several of them (the counter of outstanding loads drains in order): the node ids
-  // of the lane's dofs, then K_p (every element the thread stages, into registers), then --
-  // once the ids are in -- the displacements; K_p goes to LDS while those are in flight.
+  // K_p is staged in LDS first, in batches of a few elements per thread (few registers: a CU
+  // then holds six blocks, so the items of a step mostly fit in one round of blocks), then the
+  // lane gathers its cell's displacements.
   const int n_k = nd * nd;
   using GT = typename std::conditional<PREC == 0, double, float>::type;  // K32: FP32 or 16-bit-rounded
-  constexpr int kKMax = (kHangMaxDof * kHangMaxDof + 255) / 256;  // K elements per thread (24)
-  GT kv[kKMax];
-  auto load_k = [&]() {
-    const gptr_t<GT> K = as_global(PREC == 0 ? (const GT*)(a.K64 + it.koff) : (const GT*)(a.K32 + it.koff));
-#pragma unroll
-    for (int b = 0; b < kKMax; ++b) {
-      const int e = b * 256 + tid;
-      kv[b] = e < n_k ? K[e] : GT(0);
-    }
-  };
   const float inv_nd = 1.0f / (float)nd;
   auto put_k = [&](int e, GT v) {
     const int r = (int)(((float)e + 0.5f) * inv_nd);  // exact for e < 2^22
@@ -203,16 +192,7 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
     }
     for (int e = tid; e < (rows - nd) * nd; e += 256) Kl[(nd + e / nd) * KP + e % nd] = KT(0);
   };
-  // K_p into LDS, rows and columns zero-padded to whole tiles
-  auto store_k = [&]() {
-#pragma unroll
-    for (int b = 0; b < kKMax; ++b) {
-      const int e = b * 256 + tid;
-      if (e < n_k) put_k(e, kv[b]);
-    }
-    pad_k();
-  };
-  // the same in batches of 8 elements per thread (fewer registers, one round trip per batch)
+  // K_p into LDS, rows and columns zero-padded to whole tiles, 8 elements per thread at a time
   auto stage_k_batched = [&]() {
     const gptr_t<GT> K = as_global(PREC == 0 ? (const GT*)(a.K64 + it.koff) : (const GT*)(a.K32 + it.koff));
     constexpr int kBatch = 8;
@@ -242,22 +222,18 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
     // dofs j = 4 t + p have component (t + p) mod 3: the output rotation
     const HangRot hi = hang_rot<STATE, PREC != 0>(a, p % 3, p0, p1, p2, s0, s1, s2, g0, live);
     const int jmax = live ? nd : 0;
-    // FP64: K_p staged first (holding it in registers across the gathers would halve the
-    // blocks per CU)
-    if constexpr (PREC == 0) stage_k_batched();
+    stage_k_batched();
     int32_t gi[TMAX];
     static_for<TMAX>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       const int j = 4 * t + p;
       gi[t] = t < T && j < jmax ? conn[it.conn0 + (int64_t)(j / 3) * it.count + c] : -1;
     });
-    if constexpr (PREC != 0) load_k();
     static_for<TMAX>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       b[t] = VT(0);
       if (gi[t] >= 0) b[t] = (VT)hang_dof_at<STATE, t % 3>(a, gi[t], hi);
     });
-    if constexpr (PREC != 0) store_k();
     __syncthreads();  // K staged
     using AT = typename std::conditional<PREC == 0, mma_d4, mma_f4>::type;
     AT acc[kHangRowTiles];
@@ -310,7 +286,7 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
         gi[t][i] = t < T && j < jmax ? conn[it.conn0 + (int64_t)(j / 3) * it.count + c] : -1;
       });
     });
-    load_k();
+    stage_k_batched();
     static_for<TMAX>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       static_for<8>([&](auto ic) {
@@ -320,7 +296,6 @@ __global__ void __launch_bounds__(256) tiled_hang_mma(MeshRef single, const Mesh
         mx = fmaxf(mx, fabsf(u[t][i]));
       });
     });
-    store_k();
     // FP16: a power of two per cell brings its largest value into [1, 2) (the cell's dofs are
     // spread over the lanes q, q + 16, q + 32, q + 48)
     float scale = 1.0f;

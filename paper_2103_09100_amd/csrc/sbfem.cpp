@@ -559,9 +559,11 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
       if (!regular(c)) hcells.push_back(c);
     std::stable_sort(hcells.begin(), hcells.end(),
                      [&](int64_t x, int64_t y) { return d->pattern[x] < d->pattern[y]; });
-    // the items of one hanging-pass block share a pattern: each pattern's items are padded with
-    // empty items to whole blocks; the block stages that pattern's matrix in LDS
-    const int per_block = P.block_threads_mixed / sbfem::kWave;
+    // the items of one block of the VALU hanging pass share a pattern: each pattern's items are
+    // padded with empty items to whole blocks, and the block stages that pattern's matrix in
+    // LDS (the matrix-core pass takes one item per block and needs no padding)
+    if (const char* ev = std::getenv("SBFEM_HANG")) P.hang_mma = std::strcmp(ev, "valu") != 0;
+    const int per_block = P.hang_mma ? 1 : P.block_threads_mixed / sbfem::kWave;
     std::vector<std::pair<int64_t, sbfem::HangPair>> tpairs;  // (tile, pair)
     int64_t kl_max = 0;  // entries of the largest staged matrix (rows padded to 4)
     for (size_t i0 = 0; i0 < hcells.size();) {
@@ -606,7 +608,6 @@ sbfem_status plan_mesh(const sbfem_patterns* p, const sbfem_mesh_desc* d, MeshPl
         while (P.hitems.size() % per_block) P.hitems.push_back(pad);
       }
     }
-    if (const char* ev = std::getenv("SBFEM_HANG")) P.hang_mma = std::strcmp(ev, "valu") != 0;
     if (P.hang_mma) {
       P.lds_hang = 0;
       for (const auto& it : P.hitems) P.lds_hang = std::max<int64_t>(P.lds_hang, sbfem::hang_mma_lds_bytes(d->prod, 3 * it.nn));
