@@ -643,9 +643,10 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
 // thread, halo nodes two per thread), the halo ids are the block's first loads.
 // PROD: sbfem_prod of the Walsh product (FP64; FP32; FP16 / BF16 operands with FP32
 // arithmetic); STATE: sbfem_state of u_n, u_{n-1} (and of the inverse mass: FP32 with FP32
-// state, else FP64).
+// state, else FP64).  The reduced-product forms fit 80 VGPRs (6 waves per SIMD: three blocks
+// per CU); the compensated state asks for that bound, which it would otherwise just miss.
 template <int PROD, int STATE>
-__global__ void __launch_bounds__(512) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
+__global__ void __launch_bounds__(512, PROD != 0 && STATE == 2 ? 6 : 1) tiled_step8(MeshRef single, const MeshRef* __restrict__ refs,
                                                    const TileWork* __restrict__ work, int64_t first,
                                                    int64_t count, int64_t k, int force_only) {
   extern __shared__ double lds[];
