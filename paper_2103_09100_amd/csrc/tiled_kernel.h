@@ -253,9 +253,15 @@ __device__ __forceinline__ void tile_loads(const TiledArgs& a, const OwnerTile& 
 // Forces of hanging-node cells on the tile's owned dofs, from the hanging-cell pass (stored
 // in FP64 for FP64 products, else in FP32).  A tile next to refined regions holds thousands
 // of such rows.  With ROWS > 1 each thread takes ROWS pairs at a time (their loads, then their
-// forces, then the sums), so that a round trip serves ROWS rows; that form is measured faster
-// for every product and state form except FP32 products with FP64 state, whose kernel is
-// faster with one row at a time.
+// forces, then the sums), so that a round trip serves ROWS rows.  The best ROWS was measured
+// per kernel on the pattern-rich and the inclusion meshes (it changes the code the compiler
+// schedules around the item loop): four for FP64 products, the compensated state and FP32
+// products with FP32 state, two for FP32 products with FP64 state, one for the 16-bit forms
+// with FP64 or FP32 state.
+template <int PROD, int STATE>
+__host__ __device__ constexpr int hang_rows_per_round() {
+  return PROD == 0 || STATE == 2 || (PROD == 1 && STATE == 1) ? 4 : (PROD == 1 ? 2 : 1);
+}
 template <bool FP32, int ROWS>
 __device__ __forceinline__ void tile_hang_forces(const TiledArgs& a, const OwnerTile& tile, double* fl, int tid,
                                                  int nt) {
@@ -620,7 +626,7 @@ __device__ __forceinline__ void owner_tile(const TiledArgs& a, const OwnerTile& 
     tile_stage<FP32, STATE>(a, tile, ul, fl, tid, nt);
   __syncthreads();
   if (!force_only) tile_loads(a, tile, step, fl, tid, nt);
-  tile_hang_forces<FP32, PROD == 1 && STATE == 0 ? 1 : 4>(a, tile, fl, tid, nt);
+  tile_hang_forces<FP32, hang_rows_per_round<PROD, STATE>()>(a, tile, fl, tid, nt);
   while (w < tile.n_items) {
     // the next record is requested before this cell's work
     const int wn = w + n_waves;
